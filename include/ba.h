@@ -1,0 +1,132 @@
+/*
+ * ba.h -- C ABI of libba, a gfx950 (MI355X) generator of Barabasi-Albert
+ * graphs by per-edge recomputation (Sanders & Schulz, "Scalable Generation of
+ * Scale-free Graphs", arXiv:1602.07106).
+ *
+ * The graph (paper Section 2): an empty seed graph, n nodes, d edges per
+ * node, m = n*d edges, self-loops and parallel edges allowed.  The edge array
+ * E[0 .. 2m-1] holds edge i at positions 2i (first endpoint) and 2i+1
+ * (second endpoint):
+ *
+ *   E[2i]   = floor(i / d)
+ *   E[2i+1] = E[x] with x = h(2i+1) in 0..2i              (Batagelj-Brandes)
+ *
+ * which the library evaluates per edge, without reading E (paper Section 2,
+ * figure generateEdge): r = 2i+1, then r = h(r) at least once and until r is
+ * even, and edge i is (floor(i/d), floor(r/(2d))).  The keyed hash is
+ *
+ *   key  = seed * 0x9E3779B97F4A7C15                      (mod 2^64)
+ *   h(r) = umul64hi(fmix64(r XOR key), r)                 (a value in 0..r-1)
+ *
+ * with fmix64 the SplitMix64 output mix and umul64hi the high 64 bits of the
+ * 128-bit product.  The result depends only on (n, d, seed): never on the
+ * stream, the launch shape or how a range is split (paper Section 2: the graph
+ * depends on the hash function, not on the number of processors).
+ *
+ * Conventions for every entry point:
+ *  - Pointers named as device pointers must be device memory of the current
+ *    HIP device, owned by the caller; the library never allocates or frees.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls are
+ *    asynchronous: outputs are valid once the stream reaches the call.
+ *    Execution errors surface at the caller's next synchronisation.
+ *  - Argument checks run on the host before any launch; on error nothing is
+ *    launched and no output is touched.
+ *  - m = 0 (n = 0 or d = 0) is valid; the call then only writes the outputs
+ *    that have a defined value (zero degrees, zero checksum).
+ *  - Calls on different streams may run concurrently; the library keeps no
+ *    mutable state other than a thread-local last HIP error code.
+ */
+#ifndef BA_H
+#define BA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define BA_OK 0
+#define BA_EINVAL (-1)  /* null or misaligned buffer, range past m, first_k > n */
+#define BA_ERANGE (-2)  /* 2*n*d does not fit 64 bits, or node IDs do not fit the output type */
+#define BA_EDEVICE (-4) /* a HIP call failed; ba_last_hip_error() gives its hipError_t */
+
+/*
+ * The whole edge array of the graph (n, d, seed), paper Section 2.
+ *   edges : device, uint32[2*n*d], written in full: edges[2i] = E[2i],
+ *           edges[2i+1] = E[2i+1].  4-byte aligned (16-byte aligned is faster).
+ *   deg   : device, uint32[n] or NULL.  When not NULL it is overwritten with
+ *           deg[v] = number of positions p with E[p] = v (a self-loop counts
+ *           twice; the degrees sum to 2m).  Computed in the same pass.
+ * Errors: BA_ERANGE if n > 2^32 or 2*n*d >= 2^64; BA_EINVAL if a needed
+ * pointer is NULL or misaligned.
+ */
+int ba_generate(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint32_t *deg,
+                void *stream);
+
+/*
+ * Edges edge_begin .. edge_begin+edge_count-1 of the graph (n, d, seed).
+ * Chunks of a graph generated in any order and concatenate to ba_generate's
+ * array: the per-edge independence of paper Section 2 (and its load
+ * balancing by batches of edge IDs).
+ *   edges : device, uint32[2*edge_count]; edges[2j], edges[2j+1] = edge
+ *           edge_begin+j.
+ *   deg   : device, uint32[n] or NULL.  When not NULL the counts of both
+ *           endpoints of every edge in the range are ADDED to it (the caller
+ *           initialises it, e.g. to zero), so chunks accumulate to the
+ *           degrees of the whole graph.
+ * Errors: as ba_generate, plus BA_EINVAL if edge_begin+edge_count > n*d.
+ */
+int ba_generate_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin,
+                      uint64_t edge_count, uint32_t *edges, uint32_t *deg, void *stream);
+
+/*
+ * As ba_generate_range with 64-bit node IDs (any n with 2*n*d < 2^64).
+ *   edges : device, uint64[2*edge_count], 8-byte aligned.
+ */
+int ba_generate_range_u64(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin,
+                          uint64_t edge_count, uint64_t *edges, void *stream);
+
+/*
+ * Streaming consumer of paper Section 3: degrees of the first first_k nodes
+ * of the graph (n, d, seed) without storing any edge, plus an edge checksum.
+ *   deg          : device, uint64[first_k], overwritten with the degrees of
+ *                  nodes 0..first_k-1 (same convention as ba_generate).
+ *   xor_checksum : device, uint64[1] or NULL; overwritten with the XOR over
+ *                  all edges i of w_i = (u_i * 2^32 + v_i) * (2i+1) mod 2^64,
+ *                  (u_i, v_i) = edge i.
+ * Errors: BA_EINVAL if first_k > n or deg is NULL with first_k > 0;
+ * BA_ERANGE if 2*n*d >= 2^64.
+ */
+int ba_degrees(uint64_t n, uint32_t d, uint64_t seed, uint64_t first_k, uint64_t *deg,
+               uint64_t *xor_checksum, void *stream);
+
+/*
+ * ba_degrees over the edges edge_begin .. edge_begin+edge_count-1 only,
+ * ACCUMULATING: endpoint counts are added to deg[0..first_k-1] and the edge
+ * words are XORed into *xor_checksum.  Ranges that partition 0..n*d-1 give
+ * exactly ba_degrees' result from zeroed outputs.
+ */
+int ba_degrees_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin,
+                     uint64_t edge_count, uint64_t first_k, uint64_t *deg,
+                     uint64_t *xor_checksum, void *stream);
+
+/* Text for a status code (static storage, never NULL). */
+const char *ba_strerror(int status);
+
+/* hipError_t of the last failed HIP call made by this thread, 0 if none. */
+int ba_last_hip_error(void);
+
+/*
+ * Host-side self-test of the exact division by d the kernels use for
+ * floor(i/d) and floor(r/(2d)) (multiply-high method of Granlund & Montgomery,
+ * PLDI 1994).  Writes q[j] = floor(x[j] / d) computed that way, on the host,
+ * for count host values.  d >= 1.  Returns BA_OK or BA_EINVAL.
+ */
+int ba_host_divide(uint32_t d, const uint64_t *x, uint64_t *q, uint64_t count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BA_H */

@@ -1,0 +1,214 @@
+"""Barabasi-Albert graph generation by per-edge recomputation on MI355X.
+
+Thin Python binding over libba.so (C ABI in include/ba.h).  Every step of the
+generator runs in the library's HIP kernels; this module only allocates torch
+device tensors, passes their pointers and the current HIP stream, and turns
+status codes into exceptions.  There is no CPU fallback: without the built
+library every call raises.
+
+The graph (Sanders & Schulz, arXiv:1602.07106, Section 2): n nodes, d edges
+per node, empty seed graph, self-loops and parallel edges allowed.  Edge i is
+(floor(i/d), E[2i+1]) where E[2i+1] follows r = 2i+1, r = h(r), ... until r is
+even and is floor(r/(2d)); h(r) = umul64hi(fmix64(r ^ seed*phi64), r).
+
+Tensors: node IDs of the uint32 paths are returned in int32 tensors holding
+the uint32 bit patterns (identical values for n <= 2^31); uint64 results
+(64-bit IDs, degrees, checksums) are returned in int64 tensors holding the
+uint64 bit patterns.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import torch
+
+from . import build as _build
+
+__all__ = [
+    "BAError",
+    "generate",
+    "generate_range",
+    "generate_range_u64",
+    "degrees",
+    "degrees_range",
+    "lib",
+    "library_path",
+]
+
+BA_OK, BA_EINVAL, BA_ERANGE, BA_EDEVICE = 0, -1, -2, -4
+
+
+class BAError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        L = lib()
+        msg = L.ba_strerror(status).decode()
+        if status == BA_EDEVICE:
+            msg += " (hipError_t %d)" % L.ba_last_hip_error()
+        super().__init__("%s: %s" % (fn, msg))
+        self.status = status
+
+
+_u64, _u32, _p, _int = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
+_SIGS = {
+    "ba_generate": (_int, [_u64, _u32, _u64, _p, _p, _p]),
+    "ba_generate_range": (_int, [_u64, _u32, _u64, _u64, _u64, _p, _p, _p]),
+    "ba_generate_range_u64": (_int, [_u64, _u32, _u64, _u64, _u64, _p, _p]),
+    "ba_degrees": (_int, [_u64, _u32, _u64, _u64, _p, _p, _p]),
+    "ba_degrees_range": (_int, [_u64, _u32, _u64, _u64, _u64, _u64, _p, _p, _p]),
+    "ba_strerror": (ctypes.c_char_p, [_int]),
+    "ba_last_hip_error": (_int, []),
+    "ba_host_divide": (_int, [_u32, _p, _p, _u64]),
+}
+
+_lib = None
+
+
+def library_path() -> str:
+    return _build.LIB
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libba.so (built first if it does not exist)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, status: int) -> None:
+    if status != BA_OK:
+        raise BAError(fn, status)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _device(device) -> torch.device:
+    dev = torch.device("cuda" if device is None else device)
+    if dev.type != "cuda":
+        raise ValueError("the generator runs on the GPU only")
+    return dev
+
+
+def generate(
+    n: int,
+    d: int,
+    seed: int,
+    *,
+    degrees: bool = False,
+    out: Optional[torch.Tensor] = None,
+    deg_out: Optional[torch.Tensor] = None,
+    device=None,
+) -> Tuple[torch.Tensor, Optional[torch.Tensor]]:
+    """Whole edge list of (n, d, seed) as int32[n*d, 2] (uint32 IDs), and the
+    degree array int32[n] (uint32 counts) when ``degrees``.  ``out`` /
+    ``deg_out`` may supply preallocated contiguous int32 tensors."""
+    dev = _device(device if out is None else out.device)
+    m = n * d
+    if out is None:
+        out = torch.empty((m, 2), dtype=torch.int32, device=dev)
+    elif out.dtype != torch.int32 or out.numel() != 2 * m:
+        raise ValueError("out must be int32 with 2*n*d elements")
+    deg = None
+    if degrees:
+        deg = deg_out if deg_out is not None else torch.empty(n, dtype=torch.int32, device=dev)
+        if deg.dtype != torch.int32 or deg.numel() != n:
+            raise ValueError("deg_out must be int32 with n elements")
+    with torch.cuda.device(dev):
+        _check("ba_generate", lib().ba_generate(n, d, seed, _ptr(out), _ptr(deg), _stream(dev)))
+    return out, deg
+
+
+def generate_range(
+    n: int,
+    d: int,
+    seed: int,
+    begin: int,
+    count: int,
+    *,
+    deg: Optional[torch.Tensor] = None,
+    out: Optional[torch.Tensor] = None,
+    device=None,
+) -> torch.Tensor:
+    """Edges begin..begin+count-1 as int32[count, 2].  When ``deg`` (int32[n])
+    is given, both endpoints of every edge in the range are added to it."""
+    dev = _device(device if out is None else out.device)
+    if out is None:
+        out = torch.empty((count, 2), dtype=torch.int32, device=dev)
+    elif out.dtype != torch.int32 or out.numel() != 2 * count:
+        raise ValueError("out must be int32 with 2*count elements")
+    if deg is not None and (deg.dtype != torch.int32 or deg.numel() != n):
+        raise ValueError("deg must be int32 with n elements")
+    with torch.cuda.device(dev):
+        _check(
+            "ba_generate_range",
+            lib().ba_generate_range(n, d, seed, begin, count, _ptr(out), _ptr(deg), _stream(dev)),
+        )
+    return out
+
+
+def generate_range_u64(n: int, d: int, seed: int, begin: int, count: int, *, device=None) -> torch.Tensor:
+    """Edges begin..begin+count-1 with 64-bit IDs as int64[count, 2]."""
+    dev = _device(device)
+    out = torch.empty((count, 2), dtype=torch.int64, device=dev)
+    with torch.cuda.device(dev):
+        _check(
+            "ba_generate_range_u64",
+            lib().ba_generate_range_u64(n, d, seed, begin, count, _ptr(out), _stream(dev)),
+        )
+    return out
+
+
+def degrees(n: int, d: int, seed: int, first_k: int, *, device=None) -> Tuple[torch.Tensor, int]:
+    """Streaming degrees of nodes 0..first_k-1 (int64[first_k]) and the edge
+    XOR checksum (a Python int in 0..2^64-1); no edge is stored."""
+    dev = _device(device)
+    deg = torch.empty(first_k, dtype=torch.int64, device=dev)
+    cs = torch.empty(1, dtype=torch.int64, device=dev)
+    with torch.cuda.device(dev):
+        _check("ba_degrees", lib().ba_degrees(n, d, seed, first_k, _ptr(deg), _ptr(cs), _stream(dev)))
+    return deg, int(cs.item()) & ((1 << 64) - 1)
+
+
+def degrees_range(
+    n: int,
+    d: int,
+    seed: int,
+    begin: int,
+    count: int,
+    first_k: int,
+    deg: torch.Tensor,
+    cs: Optional[torch.Tensor] = None,
+) -> None:
+    """Accumulating form of :func:`degrees` over edges begin..begin+count-1:
+    adds endpoint counts into ``deg`` (int64[first_k]) and XORs the edge words
+    into ``cs`` (int64[1]) when given."""
+    dev = deg.device
+    if deg.dtype != torch.int64 or deg.numel() != first_k:
+        raise ValueError("deg must be int64 with first_k elements")
+    if cs is not None and (cs.dtype != torch.int64 or cs.numel() != 1):
+        raise ValueError("cs must be int64 with one element")
+    with torch.cuda.device(dev):
+        _check(
+            "ba_degrees_range",
+            lib().ba_degrees_range(n, d, seed, begin, count, first_k, _ptr(deg), _ptr(cs), _stream(dev)),
+        )

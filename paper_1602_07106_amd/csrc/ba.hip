@@ -1,0 +1,561 @@
+// ba.hip -- gfx950 kernels and the C ABI of libba (declared in include/ba.h).
+//
+// The method (paper Section 2, figure generateEdge): edge i of a
+// Barabasi-Albert graph with an empty seed graph is computed on its own, with
+// no access to the edge array: r = 2i+1, then r = h(r) (at least once) until r
+// is even, and the edge is (floor(i/d), floor(r/(2d))).  Edges are
+// independent units, so a launch is a set of waves that each own a
+// contiguous run of edge IDs (the batches of edge IDs of paper Section 2).
+//
+// Wavefront-level refill.  The number of hash steps of an edge is geometric
+// with mean about 2 (paper Section 2: P(more than k steps) <= 2^-k).  One
+// edge per lane would keep a wave64 busy for the longest of 64 chains
+// (about 7 steps) for 2 steps of useful work per lane.  Instead each lane runs
+// one chain step per iteration; a lane whose chain ends hands its result to
+// LDS and takes the next unclaimed edge of its wave's tile (ballot + mbcnt
+// give every finishing lane a distinct next edge).  All lanes stay busy
+// until the tile runs dry.
+//
+// Output.  The stored kernel writes edge pairs (u, v) as uint32.  Finished
+// chains leave floor(r/2) (narrow path) or v (wide path) in a per-wave LDS
+// tile; when the tile is complete the wave writes it out as 16-byte
+// (two-edge) coalesced stores, computing u = floor(i/d) and v on the way.
+// The fused degree histogram adds one per second endpoint with a global
+// atomic (first endpoints contribute exactly d per node, in closed form).
+//
+// The streaming kernel (paper Section 3) stores nothing: each finished edge
+// updates the degree counts of the first k nodes (an LDS-privatised table for
+// the hottest low IDs, 64-bit global atomics above) and a per-lane XOR
+// checksum, reduced per wave at the end.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "ba_device.h"
+#include "../../include/ba.h"
+
+namespace ba {
+
+constexpr int kWave = 64;
+constexpr int kGenBlock = 256;  // 4 waves
+constexpr int kGenWaves = kGenBlock / kWave;
+constexpr uint32_t kTile = 2048;  // edges per wave tile (8 KiB of LDS per wave)
+
+struct GenArgs {
+    HashKey key;
+    Divider div;
+    uint64_t begin;   // first edge ID of the launch
+    uint64_t count;   // number of edges
+    uint64_t ntiles;  // ceil(count / kTile)
+    uint32_t d;
+    uint32_t *edges;  // 2*count uint32
+    uint32_t *deg;    // nullable, n uint32
+};
+
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ void deg_add(uint32_t *deg, uint32_t v)
+{
+    __hip_atomic_fetch_add(deg + v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One chain step for every lane, then refill of the lanes that finished.
+// NARROW: all positions of the launch are below 2^32.
+template <bool NARROW, bool DEG, bool VEC16>
+__global__ __launch_bounds__(kGenBlock) void k_gen_u32(GenArgs a)
+{
+    __shared__ uint32_t stage_all[kGenWaves][kTile];
+    const uint32_t lane = __lane_id();
+    const uint32_t wv = threadIdx.x / kWave;
+    uint32_t *stage = stage_all[wv];
+    const uint64_t wstride = (uint64_t)gridDim.x * kGenWaves;
+
+    for (uint64_t tile = (uint64_t)blockIdx.x * kGenWaves + wv; tile < a.ntiles; tile += wstride) {
+        const uint64_t off = tile * kTile;
+        const uint32_t tn = (uint32_t)min((uint64_t)kTile, a.count - off);
+        const uint64_t ibase = a.begin + off;
+
+        uint32_t li = lane;
+        bool active = li < tn;
+        uint32_t next = kWave;
+        uint32_t remaining = tn;
+        if constexpr (NARROW) {
+            uint32_t r = 2u * ((uint32_t)ibase + li) + 1u;
+            while (remaining) {
+                r = hash_narrow(r, a.key);
+                const bool done = active && !(r & 1u);
+                const uint64_t dm = __ballot(done);
+                if (done) {
+                    stage[li] = r >> 1;
+                    li = next + lane_rank(dm);
+                    active = li < tn;
+                    r = 2u * ((uint32_t)ibase + li) + 1u;
+                }
+                const uint32_t nd = (uint32_t)__popcll(dm);
+                next += nd;
+                remaining -= nd;
+            }
+        } else {
+            uint64_t r = 2 * (ibase + li) + 1;
+            while (remaining) {
+                r = hash_wide(r, a.key);
+                const bool done = active && !(r & 1u);
+                const uint64_t dm = __ballot(done);
+                if (done) {
+                    stage[li] = (uint32_t)div64(r >> 1, a.div);
+                    li = next + lane_rank(dm);
+                    active = li < tn;
+                    r = 2 * (ibase + li) + 1;
+                }
+                const uint32_t nd = (uint32_t)__popcll(dm);
+                next += nd;
+                remaining -= nd;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+        // Flush: two edges per lane per step, 16-byte stores.
+        uint32_t *out = a.edges + 2 * off;
+        for (uint32_t j = 2 * lane; j < tn; j += 2 * kWave) {
+            const uint2 s = *reinterpret_cast<const uint2 *>(stage + j);
+            uint32_t u0, u1, v0, v1;
+            if constexpr (NARROW) {
+                const uint32_t i0 = (uint32_t)ibase + j;
+                u0 = div32(i0, a.div);
+                u1 = div32(i0 + 1, a.div);
+                v0 = div32(s.x, a.div);
+                v1 = div32(s.y, a.div);
+            } else {
+                const uint64_t i0 = ibase + j;
+                u0 = (uint32_t)div64(i0, a.div);
+                u1 = (uint32_t)div64(i0 + 1, a.div);
+                v0 = s.x;
+                v1 = s.y;
+            }
+            const bool two = j + 1 < tn;
+            if (VEC16 && two) {
+                *reinterpret_cast<uint4 *>(out + 2 * j) = make_uint4(u0, v0, u1, v1);
+            } else {
+                out[2 * j] = u0;
+                out[2 * j + 1] = v0;
+                if (two) {
+                    out[2 * j + 2] = u1;
+                    out[2 * j + 3] = v1;
+                }
+            }
+            if constexpr (DEG) {
+                deg_add(a.deg, v0);
+                if (two) deg_add(a.deg, v1);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// 64-bit node IDs, any positions: each finished chain stores its edge pair
+// directly (used for ranges of very large graphs; not the bandwidth path).
+struct Gen64Args {
+    HashKey key;
+    Divider div;
+    uint64_t begin, count;
+    uint64_t nchunks;  // ceil(count / kTile)
+    uint64_t *edges;   // 2*count uint64
+};
+
+__global__ __launch_bounds__(kGenBlock) void k_gen_u64(Gen64Args a)
+{
+    const uint32_t lane = __lane_id();
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint64_t wstride = (uint64_t)gridDim.x * kGenWaves;
+    for (uint64_t c = (uint64_t)blockIdx.x * kGenWaves + wv; c < a.nchunks; c += wstride) {
+        const uint64_t off = c * kTile;
+        const uint32_t tn = (uint32_t)min((uint64_t)kTile, a.count - off);
+        const uint64_t ibase = a.begin + off;
+        uint32_t li = lane;
+        bool active = li < tn;
+        uint32_t next = kWave, remaining = tn;
+        uint64_t r = 2 * (ibase + li) + 1;
+        while (remaining) {
+            r = hash_wide(r, a.key);
+            const bool done = active && !(r & 1u);
+            const uint64_t dm = __ballot(done);
+            if (done) {
+                const uint64_t i = ibase + li;
+                uint64_t *o = a.edges + 2 * (off + li);
+                o[0] = div64(i, a.div);
+                o[1] = div64(r >> 1, a.div);
+                li = next + lane_rank(dm);
+                active = li < tn;
+                r = 2 * (ibase + li) + 1;
+            }
+            const uint32_t nd = (uint32_t)__popcll(dm);
+            next += nd;
+            remaining -= nd;
+        }
+    }
+}
+
+// deg[v] = d for v < n (first endpoints of a whole graph, in closed form).
+__global__ void k_fill_u32(uint32_t *p, uint64_t count, uint32_t value)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < count; j += stride)
+        p[j] = value;
+}
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t count, uint64_t value)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < count; j += stride)
+        p[j] = value;
+}
+
+// First-endpoint counts of the edges b .. b+c-1 for nodes v0 .. v1-1: node v
+// is the first endpoint of edges v*d .. v*d+d-1.
+template <class T>
+__global__ void k_first_endpoints(T *deg, uint64_t v0, uint64_t v1, uint64_t b, uint64_t c,
+                                  uint64_t d)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = v0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < v1; v += stride) {
+        const uint64_t lo = max(b, v * d), hi = min(b + c, v * d + d);
+        if (hi > lo) atomicAdd(deg + v, (T)(hi - lo));
+    }
+}
+
+// ------------------------------------------------------------ streaming
+
+constexpr int kStreamBlock = 1024;  // 16 waves share one LDS degree table
+constexpr int kStreamWaves = kStreamBlock / kWave;
+constexpr uint32_t kLdsNodes = 16384;  // LDS-privatised degree counters per block
+
+struct StreamArgs {
+    HashKey key;
+    Divider div;
+    uint64_t begin, count;
+    uint64_t per_wave;  // edges per wave (multiple of 64)
+    uint64_t k;         // first_k
+    uint32_t klds;      // min(k, kLdsNodes)
+    uint64_t *deg;      // first_k uint64 (second endpoints added here)
+    uint64_t *cs;       // nullable
+};
+
+template <bool NARROW>
+__global__ __launch_bounds__(kStreamBlock) void k_stream(StreamArgs a)
+{
+    __shared__ uint32_t cnt[kLdsNodes];
+    for (uint32_t v = threadIdx.x; v < a.klds; v += kStreamBlock) cnt[v] = 0;
+    __syncthreads();
+
+    const uint32_t lane = __lane_id();
+    const uint64_t gw = (uint64_t)blockIdx.x * kStreamWaves + threadIdx.x / kWave;
+    const uint64_t w0 = gw * a.per_wave;
+    uint64_t xs = 0;
+    if (w0 < a.count) {
+        const uint64_t wn = min(a.per_wave, a.count - w0);
+        const uint64_t ibase = a.begin + w0;
+        uint64_t li = lane;
+        bool active = li < wn;
+        uint64_t next = kWave, remaining = wn;
+        uint64_t r = 2 * (ibase + li) + 1;
+        while (remaining) {
+            if constexpr (NARROW)
+                r = hash_narrow((uint32_t)r, a.key);
+            else
+                r = hash_wide(r, a.key);
+            const bool done = active && !(r & 1u);
+            const uint64_t dm = __ballot(done);
+            if (done) {
+                const uint64_t i = ibase + li;
+                const uint64_t v = NARROW ? (uint64_t)div32((uint32_t)(r >> 1), a.div)
+                                          : div64(r >> 1, a.div);
+                const uint64_t u = NARROW ? (uint64_t)div32((uint32_t)i, a.div) : div64(i, a.div);
+                if (v < a.klds)
+                    atomicAdd(&cnt[v], 1u);
+                else if (v < a.k)
+                    __hip_atomic_fetch_add(a.deg + v, (uint64_t)1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                xs ^= ((u << 32) + v) * (2 * i + 1);
+                li = next + lane_rank(dm);
+                active = li < wn;
+                r = 2 * (ibase + li) + 1;
+            }
+            const uint32_t nd = (uint32_t)__popcll(dm);
+            next += nd;
+            remaining -= nd;
+        }
+    }
+    if (a.cs) {
+        for (int o = 32; o > 0; o >>= 1) xs ^= __shfl_xor(xs, o);
+        if (lane == 0 && xs) __hip_atomic_fetch_xor(a.cs, xs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    for (uint32_t v = threadIdx.x; v < a.klds; v += kStreamBlock) {
+        const uint32_t c = cnt[v];
+        if (c) __hip_atomic_fetch_add(a.deg + v, (uint64_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// ------------------------------------------------------------ host side
+
+static thread_local int g_last_hip = 0;
+
+static int hip_check(hipError_t e)
+{
+    if (e != hipSuccess) {
+        g_last_hip = (int)e;
+        return BA_EDEVICE;
+    }
+    return BA_OK;
+}
+
+// Resident blocks per CU of a kernel, times the CU count: the persistent
+// grid.  Waves take units round-robin, so a grid larger than what is resident
+// would leave late blocks running alone at the end.
+template <class K>
+static int persistent_grid(K kernel, int block, uint32_t *grid)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    int rc = hip_check(hipGetDevice(&dev));
+    if (rc) return rc;
+    rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (rc) return rc;
+    rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0));
+    if (rc) return rc;
+    if (per_cu < 1) per_cu = 1;
+    *grid = (uint32_t)(cus * per_cu);
+    return BA_OK;
+}
+
+// 2*n*d must fit 64 bits (positions are 64-bit).
+static bool graph_fits(uint64_t n, uint32_t d, uint64_t *m)
+{
+    unsigned __int128 mm = (unsigned __int128)n * d;
+    if (mm >> 63) return false;
+    *m = (uint64_t)mm;
+    return true;
+}
+
+static uint32_t grid_for(uint64_t units, uint64_t per_block, uint64_t cap)
+{
+    uint64_t b = (units + per_block - 1) / per_block;
+    if (b > cap) b = cap;
+    if (b == 0) b = 1;
+    return (uint32_t)b;
+}
+
+template <bool N, bool D, bool V>
+static int launch_gen_one(const GenArgs &a, hipStream_t st)
+{
+    uint32_t grid = 0;
+    int rc = persistent_grid(k_gen_u32<N, D, V>, kGenBlock, &grid);
+    if (rc) return rc;
+    grid = grid_for(a.ntiles, kGenWaves, grid);
+    hipLaunchKernelGGL((k_gen_u32<N, D, V>), dim3(grid), dim3(kGenBlock), 0, st, a);
+    return hip_check(hipGetLastError());
+}
+
+static int launch_gen_u32(uint64_t begin, uint64_t count, uint32_t d, uint64_t seed, uint32_t *edges,
+                          uint32_t *deg, hipStream_t st)
+{
+    if (count == 0) return BA_OK;
+    GenArgs a{};
+    a.key = make_hash_key(seed);
+    a.div = make_divider(d);
+    a.begin = begin;
+    a.count = count;
+    a.ntiles = (count + kTile - 1) / kTile;
+    a.d = d;
+    a.edges = edges;
+    a.deg = deg;
+    const bool narrow = 2 * (begin + count) <= ((uint64_t)1 << 32);
+    const bool vec16 = ((uintptr_t)edges & 15) == 0;
+    const int sel = (narrow ? 4 : 0) | (deg ? 2 : 0) | (vec16 ? 1 : 0);
+    switch (sel) {
+    case 7: return launch_gen_one<true, true, true>(a, st);
+    case 6: return launch_gen_one<true, true, false>(a, st);
+    case 5: return launch_gen_one<true, false, true>(a, st);
+    case 4: return launch_gen_one<true, false, false>(a, st);
+    case 3: return launch_gen_one<false, true, true>(a, st);
+    case 2: return launch_gen_one<false, true, false>(a, st);
+    case 1: return launch_gen_one<false, false, true>(a, st);
+    default: return launch_gen_one<false, false, false>(a, st);
+    }
+}
+
+template <class T>
+static int launch_first_endpoints(T *deg, uint64_t n, uint64_t begin, uint64_t count, uint32_t d,
+                                  uint64_t node_limit, hipStream_t st)
+{
+    if (count == 0 || d == 0) return BA_OK;
+    uint64_t v0 = begin / d, v1 = (begin + count - 1) / d + 1;
+    if (v1 > n) v1 = n;
+    if (v1 > node_limit) v1 = node_limit;
+    if (v0 >= v1) return BA_OK;
+    const uint32_t grid = grid_for(v1 - v0, 256, 4096);
+    hipLaunchKernelGGL((k_first_endpoints<T>), dim3(grid), dim3(256), 0, st, deg, v0, v1, begin, count,
+                       (uint64_t)d);
+    return hip_check(hipGetLastError());
+}
+
+template <bool N>
+static int launch_stream_one(StreamArgs a, hipStream_t st)
+{
+    uint32_t grid = 0;
+    int rc = persistent_grid(k_stream<N>, kStreamBlock, &grid);
+    if (rc) return rc;
+    const uint64_t max_waves = (uint64_t)grid * kStreamWaves;
+    uint64_t per_wave = (a.count + max_waves - 1) / max_waves;
+    per_wave = (per_wave + kWave - 1) / kWave * kWave;
+    if (per_wave < 4 * kWave) per_wave = 4 * kWave;
+    a.per_wave = per_wave;
+    const uint64_t waves = (a.count + per_wave - 1) / per_wave;
+    grid = (uint32_t)((waves + kStreamWaves - 1) / kStreamWaves);
+    hipLaunchKernelGGL((k_stream<N>), dim3(grid), dim3(kStreamBlock), 0, st, a);
+    return hip_check(hipGetLastError());
+}
+
+static int launch_stream(uint64_t begin, uint64_t count, uint32_t d, uint64_t seed, uint64_t k,
+                         uint64_t *deg, uint64_t *cs, hipStream_t st)
+{
+    if (count == 0) return BA_OK;
+    StreamArgs a{};
+    a.key = make_hash_key(seed);
+    a.div = make_divider(d);
+    a.begin = begin;
+    a.count = count;
+    a.k = k;
+    a.klds = (uint32_t)(k < kLdsNodes ? k : kLdsNodes);
+    a.deg = deg;
+    a.cs = cs;
+    const bool narrow = 2 * (begin + count) <= ((uint64_t)1 << 32);
+    return narrow ? launch_stream_one<true>(a, st) : launch_stream_one<false>(a, st);
+}
+
+}  // namespace ba
+
+using namespace ba;
+
+extern "C" {
+
+int ba_generate(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint32_t *deg, void *stream)
+{
+    uint64_t m;
+    if (!graph_fits(n, d, &m) || n > ((uint64_t)1 << 32)) return BA_ERANGE;
+    if ((m && !edges) || ((uintptr_t)edges & 3) || ((uintptr_t)deg & 3)) return BA_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (deg && n) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256 * 8, 8192)), dim3(256), 0, st, deg, n, d);
+        int rc = hip_check(hipGetLastError());
+        if (rc) return rc;
+    }
+    return launch_gen_u32(0, m, d, seed, edges, deg, st);
+}
+
+int ba_generate_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin, uint64_t edge_count,
+                      uint32_t *edges, uint32_t *deg, void *stream)
+{
+    uint64_t m;
+    if (!graph_fits(n, d, &m) || n > ((uint64_t)1 << 32)) return BA_ERANGE;
+    if (edge_begin > m || edge_count > m - edge_begin) return BA_EINVAL;
+    if ((edge_count && !edges) || ((uintptr_t)edges & 3) || ((uintptr_t)deg & 3)) return BA_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (deg) {
+        int rc = launch_first_endpoints<uint32_t>(deg, n, edge_begin, edge_count, d, n, st);
+        if (rc) return rc;
+    }
+    return launch_gen_u32(edge_begin, edge_count, d, seed, edges, deg, st);
+}
+
+int ba_generate_range_u64(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin, uint64_t edge_count,
+                          uint64_t *edges, void *stream)
+{
+    uint64_t m;
+    if (!graph_fits(n, d, &m)) return BA_ERANGE;
+    if (edge_begin > m || edge_count > m - edge_begin) return BA_EINVAL;
+    if ((edge_count && !edges) || ((uintptr_t)edges & 7)) return BA_EINVAL;
+    if (edge_count == 0) return BA_OK;
+    Gen64Args a{};
+    a.key = make_hash_key(seed);
+    a.div = make_divider(d);
+    a.begin = edge_begin;
+    a.count = edge_count;
+    a.nchunks = (edge_count + kTile - 1) / kTile;
+    a.edges = edges;
+    uint32_t grid = 0;
+    int rc = persistent_grid(k_gen_u64, kGenBlock, &grid);
+    if (rc) return rc;
+    grid = grid_for(a.nchunks, kGenWaves, grid);
+    hipLaunchKernelGGL(k_gen_u64, dim3(grid), dim3(kGenBlock), 0, (hipStream_t)stream, a);
+    return hip_check(hipGetLastError());
+}
+
+int ba_degrees_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin, uint64_t edge_count,
+                     uint64_t first_k, uint64_t *deg, uint64_t *xor_checksum, void *stream)
+{
+    uint64_t m;
+    if (!graph_fits(n, d, &m)) return BA_ERANGE;
+    if (first_k > n || edge_begin > m || edge_count > m - edge_begin) return BA_EINVAL;
+    if ((first_k && !deg) || ((uintptr_t)deg & 7) || ((uintptr_t)xor_checksum & 7)) return BA_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (first_k) {
+        int rc = launch_first_endpoints<uint64_t>(deg, n, edge_begin, edge_count, d, first_k, st);
+        if (rc) return rc;
+    }
+    return launch_stream(edge_begin, edge_count, d, seed, first_k, deg, xor_checksum, st);
+}
+
+int ba_degrees(uint64_t n, uint32_t d, uint64_t seed, uint64_t first_k, uint64_t *deg,
+               uint64_t *xor_checksum, void *stream)
+{
+    uint64_t m;
+    if (!graph_fits(n, d, &m)) return BA_ERANGE;
+    if (first_k > n) return BA_EINVAL;
+    if ((first_k && !deg) || ((uintptr_t)deg & 7) || ((uintptr_t)xor_checksum & 7)) return BA_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (first_k) {
+        hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(first_k, 256 * 8, 4096)), dim3(256), 0, st, deg,
+                           first_k, (uint64_t)0);
+        int rc = hip_check(hipGetLastError());
+        if (rc) return rc;
+    }
+    if (xor_checksum) {
+        hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, xor_checksum, (uint64_t)1, (uint64_t)0);
+        int rc = hip_check(hipGetLastError());
+        if (rc) return rc;
+    }
+    return ba_degrees_range(n, d, seed, 0, m, first_k, deg, xor_checksum, stream);
+}
+
+const char *ba_strerror(int status)
+{
+    switch (status) {
+    case BA_OK: return "success";
+    case BA_EINVAL: return "invalid argument (null or misaligned buffer, range past n*d, or first_k > n)";
+    case BA_ERANGE: return "graph too large (2*n*d must fit 64 bits; uint32 output needs n <= 2^32)";
+    case BA_EDEVICE: return "HIP call failed (see ba_last_hip_error)";
+    default: return "unknown status";
+    }
+}
+
+int ba_last_hip_error(void) { return g_last_hip; }
+
+int ba_host_divide(uint32_t d, const uint64_t *x, uint64_t *q, uint64_t count)
+{
+    if (d == 0 || (count && (!x || !q))) return BA_EINVAL;
+    const Divider v = make_divider(d);
+    for (uint64_t j = 0; j < count; j++)
+        q[j] = (x[j] >> 32) ? div64(x[j], v) : (uint64_t)div32((uint32_t)x[j], v);
+    return BA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+"""Host-side checks of libba (no GPU needed): the library loads, exports every
+function include/ba.h declares, validates arguments before touching the
+device, and its exact divider (used by the kernels for floor(i/d) and
+floor(r/(2d))) agrees with integer division."""
+import ctypes
+import os
+import random
+import re
+
+import numpy as np
+import pytest
+
+import paper_1602_07106_amd as ba
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ba.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ba_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    L = ba.lib()
+    names = _declared()
+    assert "ba_generate" in names and "ba_degrees" in names and len(names) >= 8
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_strerror_covers_every_status():
+    L = ba.lib()
+    for st in [ba.BA_OK, ba.BA_EINVAL, ba.BA_ERANGE, ba.BA_EDEVICE, 12345]:
+        assert L.ba_strerror(st)
+    assert L.ba_strerror(12345) == b"unknown status"
+
+
+def _host_divide(d, xs):
+    x = np.ascontiguousarray(np.asarray(xs, dtype=np.uint64))
+    q = np.zeros_like(x)
+    rc = ba.lib().ba_host_divide(d, x.ctypes.data, q.ctypes.data, x.size)
+    assert rc == 0
+    return [int(v) for v in q]
+
+
+def _boundary_values(d):
+    M = (1 << 64) - 1
+    vals = {0, 1, 2, d - 1, d, d + 1, 2 * d - 1, 2 * d, (1 << 31) - 1, 1 << 31, (1 << 32) - 1, 1 << 32,
+            (1 << 32) + 1, (1 << 37) - 1, (1 << 63) - 1, 1 << 63, M - 1, M}
+    for k in [1, 2, 3, 1000, (1 << 32) // d, M // d]:
+        for delta in (-1, 0, 1):
+            vals.add(k * d + delta)
+    return sorted(v for v in vals if 0 <= v <= M)
+
+
+@pytest.mark.parametrize("d", list(range(1, 65)) + [100, 127, 641, 1000003, (1 << 31) - 1, (1 << 31) + 1, (1 << 32) - 1])
+def test_exact_division_on_boundaries(d):
+    xs = _boundary_values(d)
+    assert _host_divide(d, xs) == [x // d for x in xs]
+
+
+def test_exact_division_random():
+    rng = random.Random(5)
+    for _ in range(200):
+        d = rng.randint(1, (1 << 32) - 1) if rng.random() < 0.5 else rng.randint(1, 200)
+        xs = [rng.getrandbits(rng.choice([16, 31, 32, 33, 40, 64])) for _ in range(200)]
+        assert _host_divide(d, xs) == [x // d for x in xs]
+
+
+def test_divide_rejects_zero_divisor():
+    x = np.zeros(1, dtype=np.uint64)
+    assert ba.lib().ba_host_divide(0, x.ctypes.data, x.ctypes.data, 1) == ba.BA_EINVAL
+
+
+# Argument validation returns before any HIP call, so it runs without a GPU.
+# Pointer values below are never dereferenced.
+FAKE = 1 << 20
+
+
+def test_generate_rejects_graphs_that_do_not_fit():
+    L = ba.lib()
+    assert L.ba_generate((1 << 32) + 1, 1, 0, FAKE, None, None) == ba.BA_ERANGE
+    assert L.ba_generate(1 << 62, 4, 0, FAKE, None, None) == ba.BA_ERANGE
+    assert L.ba_generate_range_u64(1 << 62, 4, 0, 0, 1, FAKE, None) == ba.BA_ERANGE
+    assert L.ba_degrees(1 << 62, 4, 0, 1, FAKE, None, None) == ba.BA_ERANGE
+
+
+def test_generate_rejects_bad_buffers():
+    L = ba.lib()
+    assert L.ba_generate(10, 2, 0, None, None, None) == ba.BA_EINVAL
+    assert L.ba_generate(10, 2, 0, FAKE + 2, None, None) == ba.BA_EINVAL
+    assert L.ba_generate(10, 2, 0, FAKE, FAKE + 1, None) == ba.BA_EINVAL
+    assert L.ba_generate_range_u64(10, 2, 0, 0, 5, FAKE + 4, None) == ba.BA_EINVAL
+    assert L.ba_degrees(10, 2, 0, 5, None, None, None) == ba.BA_EINVAL
+    assert L.ba_degrees(10, 2, 0, 5, FAKE + 4, None, None) == ba.BA_EINVAL
+
+
+def test_ranges_and_first_k_are_checked():
+    L = ba.lib()
+    assert L.ba_generate_range(10, 2, 0, 15, 6, FAKE, None, None) == ba.BA_EINVAL
+    assert L.ba_generate_range(10, 2, 0, 21, 0, FAKE, None, None) == ba.BA_EINVAL
+    assert L.ba_generate_range(10, 2, 0, (1 << 64) - 1, 2, FAKE, None, None) == ba.BA_EINVAL
+    assert L.ba_degrees(10, 2, 0, 11, FAKE, None, None) == ba.BA_EINVAL
+    assert L.ba_degrees_range(10, 2, 0, 0, 21, 5, FAKE, None, None) == ba.BA_EINVAL
+
+
+def test_empty_work_is_a_no_op():
+    L = ba.lib()
+    # m = 0 and no degree output: nothing to launch
+    assert L.ba_generate(0, 4, 0, None, None, None) == ba.BA_OK
+    assert L.ba_generate(10, 0, 0, None, None, None) == ba.BA_OK
+    assert L.ba_generate_range(10, 2, 0, 20, 0, None, None, None) == ba.BA_OK
+    assert L.ba_generate_range_u64(10, 2, 0, 3, 0, None, None) == ba.BA_OK
+    assert L.ba_degrees_range(10, 2, 0, 0, 0, 0, None, None, None) == ba.BA_OK
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+
+    with pytest.raises(ValueError):
+        ba.generate(10, 2, 0, device="cpu")

@@ -1,0 +1,145 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle,
+element by element and bit-exact (the method is integer-only, so the
+tolerance is zero)."""
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1602_07106_amd as ba  # noqa: E402
+
+M64 = (1 << 64) - 1
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _u32(t):
+    return t.cpu().numpy().view(np.uint32).reshape(-1)
+
+
+def _u64(t):
+    return t.cpu().numpy().view(np.uint64).reshape(-1)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ba.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+SMALL = [
+    (100000, 4, 1),      # the small workload, whole
+    (1, 1, 0),
+    (1, 64, 9),
+    (2, 1, 3),
+    (777, 3, 5),         # ragged tail tile
+    (5000, 33, 42),      # non-power-of-two d, several tiles
+    (4096, 16, 7),
+    (30011, 7, M64),
+    (65537, 1, 123456789),
+]
+
+
+@pytest.mark.parametrize("n,d,seed", SMALL)
+def test_generate_matches_batagelj_brandes(n, d, seed):
+    _say("generate", n, d, seed)
+    edges, deg = ba.generate(n, d, seed, degrees=True)
+    torch.cuda.synchronize()
+    E, _ = oracle.bb_generate(n, d, seed)
+    assert np.array_equal(_u32(edges), E)
+    assert np.array_equal(_u32(deg).astype(np.uint64), oracle.count_degrees(E, n))
+
+
+def test_generate_without_degrees_and_misaligned_output():
+    n, d, seed = 12345, 6, 11
+    _say("misaligned", n, d, seed)
+    E, _ = oracle.bb_generate(n, d, seed)
+    buf = torch.full((2 * n * d + 4,), -1, dtype=torch.int32, device="cuda")
+    for shift in [0, 1, 2, 3]:  # 16-byte, 4-byte, 8-byte, 4-byte aligned
+        view = buf[shift : shift + 2 * n * d]
+        ba.generate(n, d, seed, out=view)
+        torch.cuda.synchronize()
+        assert np.array_equal(_u32(view), E), shift
+
+
+def test_ranges_stitch_to_the_whole_graph_and_accumulate_degrees():
+    n, d, seed = 40000, 5, 77
+    m = n * d
+    _say("ranges", n, d, seed)
+    E, _ = oracle.bb_generate(n, d, seed)
+    deg = torch.zeros(n, dtype=torch.int32, device="cuda")
+    rng = random.Random(1)
+    cuts = sorted(rng.sample(range(1, m), 25)) + [m]
+    order = list(zip([0] + cuts[:-1], cuts))
+    rng.shuffle(order)
+    got = np.empty(2 * m, dtype=np.uint32)
+    for b, e in order:
+        out = ba.generate_range(n, d, seed, b, e - b, deg=deg)
+        torch.cuda.synchronize()
+        got[2 * b : 2 * e] = _u32(out)
+    assert np.array_equal(got, E)
+    assert np.array_equal(_u32(deg).astype(np.uint64), oracle.count_degrees(E, n))
+
+
+def test_wide_positions_beyond_2_32():
+    # positions >= 2^32 take the 64-bit hash path even for uint32 output
+    n, d, seed = 1 << 28, 16, 7
+    m = n * d
+    for b, c in [(m - 5000, 5000), ((1 << 31) - 2000, 4000), (3 << 30, 12345)]:
+        _say("wide", b, c)
+        out = ba.generate_range(n, d, seed, b, c)
+        torch.cuda.synchronize()
+        ref, _ = oracle.edges_range(d, seed, b, c)
+        assert np.array_equal(_u32(out), ref.astype(np.uint32))
+
+
+def test_u64_ids_sampled_across_the_streaming_workload():
+    n, d, seed = 1 << 30, 64, 42
+    m = n * d
+    rng = random.Random(9)
+    starts = [0, m - 3000, (1 << 31) - 77] + [rng.randrange(0, m - 3000) for _ in range(6)]
+    for b in starts:
+        _say("u64 range", b)
+        out = ba.generate_range_u64(n, d, seed, b, 3000)
+        torch.cuda.synchronize()
+        ref, _ = oracle.edges_range(d, seed, b, 3000)
+        assert np.array_equal(_u64(out), ref)
+
+
+@pytest.mark.parametrize("n,d,seed,k", [(20000, 5, 3, 1000), (100000, 4, 1, 100000), (50000, 3, 8, 20000), (1, 2, 0, 1)])
+def test_streaming_degrees_and_checksum(n, d, seed, k):
+    _say("degrees", n, d, seed, k)
+    deg, cs = ba.degrees(n, d, seed, k)
+    torch.cuda.synchronize()
+    E, _ = oracle.bb_generate(n, d, seed)
+    assert np.array_equal(_u64(deg), oracle.count_degrees(E, n)[:k])
+    assert cs == oracle.checksum_E(E)
+
+
+def test_streaming_ranges_accumulate_including_wide_positions():
+    n, d, seed, k = 1 << 30, 16, 5, 30000
+    rng = random.Random(4)
+    deg = torch.zeros(k, dtype=torch.int64, device="cuda")
+    cs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ref = np.zeros(k, dtype=np.uint64)
+    rcs = 0
+    for b, c in [(0, 200000), ((1 << 31) - 70000, 140000), ((1 << 32) - 100000, 100000),
+                 (rng.randrange(1 << 32, n * d - 50000), 50000)]:
+        _say("degrees range", b, c)
+        ba.degrees_range(n, d, seed, b, c, k, deg, cs)
+        ref, rcs, _ = oracle.stream(d, seed, b, c, k, ref, rcs)
+    torch.cuda.synchronize()
+    assert np.array_equal(_u64(deg), ref)
+    assert (int(cs.item()) & M64) == rcs
