@@ -81,6 +81,33 @@ int ba_generate_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin
                       uint64_t edge_count, uint32_t *edges, uint32_t *deg, void *stream);
 
 /*
+ * Device workspace (bytes) that ba_generate_ws / ba_generate_range_ws need to
+ * compute degrees over edge_count edges of (n, d) in one pass; 0 when
+ * edge_count is 0 or the graph does not fit.  A smaller workspace (at least
+ * what 2^20 edges need) is accepted and processed in several passes.
+ * The degree pipeline (a radix partition of second endpoints in HBM followed
+ * by LDS histograms) keeps its lists there: about 6.5 bytes per edge.
+ */
+uint64_t ba_generate_workspace_bytes(uint64_t n, uint32_t d, uint64_t edge_count);
+
+/*
+ * ba_generate / ba_generate_range with a caller-provided workspace for the
+ * degree computation (ignored when deg is NULL).
+ *   workspace : device, 256-byte aligned, workspace_bytes long, owned by the
+ *               caller; its contents are scratch (not preserved).  Calls that
+ *               share a workspace must be ordered (same stream).
+ * Without a workspace, ba_generate / ba_generate_range take one from the
+ * stream-ordered allocator (hipMallocAsync / hipFreeAsync) when deg != NULL.
+ * Errors: as the calls without workspace, plus BA_EINVAL if deg != NULL and
+ * the workspace is NULL, misaligned or smaller than a 2^20-edge pass needs.
+ */
+int ba_generate_ws(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint32_t *deg,
+                   void *workspace, uint64_t workspace_bytes, void *stream);
+int ba_generate_range_ws(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin,
+                         uint64_t edge_count, uint32_t *edges, uint32_t *deg, void *workspace,
+                         uint64_t workspace_bytes, void *stream);
+
+/*
  * As ba_generate_range with 64-bit node IDs (any n with 2*n*d < 2^64).
  *   edges : device, uint64[2*edge_count], 8-byte aligned.
  */

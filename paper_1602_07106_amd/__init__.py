@@ -28,6 +28,8 @@ from . import build as _build
 
 __all__ = [
     "BAError",
+    "workspace",
+    "workspace_bytes",
     "generate",
     "generate_range",
     "generate_range_u64",
@@ -54,6 +56,9 @@ _u64, _u32, _p, _int = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes
 _SIGS = {
     "ba_generate": (_int, [_u64, _u32, _u64, _p, _p, _p]),
     "ba_generate_range": (_int, [_u64, _u32, _u64, _u64, _u64, _p, _p, _p]),
+    "ba_generate_ws": (_int, [_u64, _u32, _u64, _p, _p, _p, _u64, _p]),
+    "ba_generate_range_ws": (_int, [_u64, _u32, _u64, _u64, _u64, _p, _p, _p, _u64, _p]),
+    "ba_generate_workspace_bytes": (_u64, [_u64, _u32, _u64]),
     "ba_generate_range_u64": (_int, [_u64, _u32, _u64, _u64, _u64, _p, _p]),
     "ba_degrees": (_int, [_u64, _u32, _u64, _u64, _p, _p, _p]),
     "ba_degrees_range": (_int, [_u64, _u32, _u64, _u64, _u64, _u64, _p, _p, _p]),
@@ -109,6 +114,24 @@ def _device(device) -> torch.device:
     return dev
 
 
+def workspace_bytes(n: int, d: int, edge_count: int) -> int:
+    """Device workspace the degree pipeline needs for edge_count edges."""
+    return int(lib().ba_generate_workspace_bytes(n, d, edge_count))
+
+
+def workspace(n: int, d: int, edge_count: int, device=None) -> torch.Tensor:
+    """A uint8 device tensor large enough for :func:`workspace_bytes`."""
+    return torch.empty(max(1, workspace_bytes(n, d, edge_count)), dtype=torch.uint8, device=_device(device))
+
+
+def _ws_arg(ws: Optional[torch.Tensor], n: int, d: int, count: int, dev: torch.device):
+    if ws is None:
+        ws = workspace(n, d, count, dev)
+    if ws.dtype != torch.uint8 or not ws.is_contiguous():
+        raise ValueError("workspace must be a contiguous uint8 tensor")
+    return ws, ws.numel()
+
+
 def generate(
     n: int,
     d: int,
@@ -117,11 +140,13 @@ def generate(
     degrees: bool = False,
     out: Optional[torch.Tensor] = None,
     deg_out: Optional[torch.Tensor] = None,
+    ws: Optional[torch.Tensor] = None,
     device=None,
 ) -> Tuple[torch.Tensor, Optional[torch.Tensor]]:
     """Whole edge list of (n, d, seed) as int32[n*d, 2] (uint32 IDs), and the
     degree array int32[n] (uint32 counts) when ``degrees``.  ``out`` /
-    ``deg_out`` may supply preallocated contiguous int32 tensors."""
+    ``deg_out`` may supply preallocated contiguous int32 tensors, ``ws`` the
+    degree pipeline's workspace (see :func:`workspace`)."""
     dev = _device(device if out is None else out.device)
     m = n * d
     if out is None:
@@ -134,7 +159,14 @@ def generate(
         if deg.dtype != torch.int32 or deg.numel() != n:
             raise ValueError("deg_out must be int32 with n elements")
     with torch.cuda.device(dev):
-        _check("ba_generate", lib().ba_generate(n, d, seed, _ptr(out), _ptr(deg), _stream(dev)))
+        if deg is None:
+            _check("ba_generate", lib().ba_generate(n, d, seed, _ptr(out), None, _stream(dev)))
+        else:
+            w, wb = _ws_arg(ws, n, d, m, dev)
+            _check(
+                "ba_generate_ws",
+                lib().ba_generate_ws(n, d, seed, _ptr(out), _ptr(deg), _ptr(w), wb, _stream(dev)),
+            )
     return out, deg
 
 
@@ -147,6 +179,7 @@ def generate_range(
     *,
     deg: Optional[torch.Tensor] = None,
     out: Optional[torch.Tensor] = None,
+    ws: Optional[torch.Tensor] = None,
     device=None,
 ) -> torch.Tensor:
     """Edges begin..begin+count-1 as int32[count, 2].  When ``deg`` (int32[n])
@@ -159,10 +192,18 @@ def generate_range(
     if deg is not None and (deg.dtype != torch.int32 or deg.numel() != n):
         raise ValueError("deg must be int32 with n elements")
     with torch.cuda.device(dev):
-        _check(
-            "ba_generate_range",
-            lib().ba_generate_range(n, d, seed, begin, count, _ptr(out), _ptr(deg), _stream(dev)),
-        )
+        if deg is None:
+            _check(
+                "ba_generate_range",
+                lib().ba_generate_range(n, d, seed, begin, count, _ptr(out), None, _stream(dev)),
+            )
+        else:
+            w, wb = _ws_arg(ws, n, d, count, dev)
+            _check(
+                "ba_generate_range_ws",
+                lib().ba_generate_range_ws(n, d, seed, begin, count, _ptr(out), _ptr(deg), _ptr(w), wb,
+                                           _stream(dev)),
+            )
     return out
 
 

@@ -143,3 +143,49 @@ def test_streaming_ranges_accumulate_including_wide_positions():
     torch.cuda.synchronize()
     assert np.array_equal(_u64(deg), ref)
     assert (int(cs.item()) & M64) == rcs
+
+
+def test_degrees_through_the_stream_ordered_allocator():
+    # ba_generate without a workspace takes one from hipMallocAsync
+    n, d, seed = 70000, 6, 21
+    _say("generate deg no-ws", n, d, seed)
+    E, _ = oracle.bb_generate(n, d, seed)
+    out = torch.empty(2 * n * d, dtype=torch.int32, device="cuda")
+    deg = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    assert ba.lib().ba_generate(n, d, seed, out.data_ptr(), deg.data_ptr(), st) == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(_u32(out), E)
+    assert np.array_equal(_u32(deg).astype(np.uint64), oracle.count_degrees(E, n))
+
+
+@pytest.mark.parametrize("scale", ["0.02", "0.5"])
+def test_degree_overflow_fallback_is_exact(scale, monkeypatch):
+    # shrunken L1 capacities push most second endpoints through the fallback
+    n, d, seed = 300000, 5, 8
+    _say("overflow", scale)
+    monkeypatch.setenv("BA_DEG_CAP_SCALE", scale)
+    E, _ = oracle.bb_generate(n, d, seed)
+    edges, deg = ba.generate(n, d, seed, degrees=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(_u32(edges), E)
+    assert np.array_equal(_u32(deg).astype(np.uint64), oracle.count_degrees(E, n))
+
+
+def test_degrees_in_several_passes_with_heavy_sub_buckets():
+    # a workspace for 2^20 edges forces 32 passes; the lowest 32768-node
+    # sub-bucket holds ~3M second endpoints, i.e. several count parts
+    n, d, seed = 1 << 22, 8, 13
+    m = n * d
+    _say("multi-pass", n, d, seed)
+    E, _ = oracle.bb_generate(n, d, seed)
+    ref = oracle.count_degrees(E, n)
+    ws = ba.workspace(n, d, 1 << 20)
+    deg = torch.zeros(n, dtype=torch.int32, device="cuda")
+    out = ba.generate_range(n, d, seed, 0, m, deg=deg, ws=ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(_u32(out), E)
+    assert np.array_equal(_u32(deg).astype(np.uint64), ref)
+    edges, deg2 = ba.generate(n, d, seed, degrees=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(_u32(deg2).astype(np.uint64), ref)
