@@ -138,6 +138,18 @@ int ba_degrees_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin,
                      uint64_t edge_count, uint64_t first_k, uint64_t *deg,
                      uint64_t *xor_checksum, void *stream);
 
+/*
+ * Measurement hook for benchmarks (not needed to generate graphs).
+ * ba_kernel_timing(1) makes every later call on this host thread record a
+ * HIP event pair on its stream around its generator kernel (the per-edge
+ * chain kernel, which dominates a call); ba_kernel_timing(0) stops and drops
+ * what was recorded.  ba_kernel_timing_read waits for the recorded events and
+ * returns the summed kernel time (ms) and the number of launches since the
+ * last enable/read, then starts a new accumulation.
+ */
+int ba_kernel_timing(int enable);
+int ba_kernel_timing_read(double *ms_total, uint64_t *launches);
+
 /* Text for a status code (static storage, never NULL). */
 const char *ba_strerror(int status);
 

@@ -33,6 +33,8 @@ __all__ = [
     "generate",
     "generate_range",
     "generate_range_u64",
+    "kernel_timing",
+    "kernel_timing_read",
     "degrees",
     "degrees_range",
     "lib",
@@ -65,6 +67,8 @@ _SIGS = {
     "ba_strerror": (ctypes.c_char_p, [_int]),
     "ba_last_hip_error": (_int, []),
     "ba_host_divide": (_int, [_u32, _p, _p, _u64]),
+    "ba_kernel_timing": (_int, [_int]),
+    "ba_kernel_timing_read": (_int, [_p, _p]),
 }
 
 _lib = None
@@ -205,6 +209,19 @@ def generate_range(
                                            _stream(dev)),
             )
     return out
+
+
+def kernel_timing(enable: bool) -> None:
+    """Start (or stop) recording HIP events around the generator kernel of
+    every call made by this thread (see ba_kernel_timing)."""
+    _check("ba_kernel_timing", lib().ba_kernel_timing(1 if enable else 0))
+
+
+def kernel_timing_read() -> Tuple[float, int]:
+    """(summed generator-kernel milliseconds, launches) since the last read."""
+    ms, n = ctypes.c_double(0.0), ctypes.c_uint64(0)
+    _check("ba_kernel_timing_read", lib().ba_kernel_timing_read(ctypes.addressof(ms), ctypes.addressof(n)))
+    return ms.value, n.value
 
 
 def generate_range_u64(n: int, d: int, seed: int, begin: int, count: int, *, device=None) -> torch.Tensor:

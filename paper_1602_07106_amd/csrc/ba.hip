@@ -33,6 +33,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <utility>
+#include <vector>
+
 #include "ba_degree.h"
 #include "ba_device.h"
 #include "../../include/ba.h"
@@ -453,6 +456,14 @@ static uint32_t grid_for(uint64_t units, uint64_t per_block, uint64_t cap)
     return (uint32_t)b;
 }
 
+// Opt-in measurement of the generator kernel (per host thread): an event
+// pair recorded on the launch stream around every generator launch.
+struct KernelTiming {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+};
+static thread_local KernelTiming g_timing;
+
 template <bool N, bool D, bool V>
 static int launch_gen_one(const GenArgs &a, hipStream_t st)
 {
@@ -460,8 +471,20 @@ static int launch_gen_one(const GenArgs &a, hipStream_t st)
     int rc = persistent_grid(k_gen_u32<N, D, V>, kGenBlock, &grid);
     if (rc) return rc;
     grid = grid_for(a.ntiles, kGenWaves, grid);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (g_timing.on) {
+        if ((rc = hip_check(hipEventCreate(&e0)))) return rc;
+        if ((rc = hip_check(hipEventCreate(&e1)))) return rc;
+        if ((rc = hip_check(hipEventRecord(e0, st)))) return rc;
+    }
     hipLaunchKernelGGL((k_gen_u32<N, D, V>), dim3(grid), dim3(kGenBlock), 0, st, a);
-    return hip_check(hipGetLastError());
+    rc = hip_check(hipGetLastError());
+    if (g_timing.on) {
+        const int rc2 = hip_check(hipEventRecord(e1, st));
+        g_timing.ev.emplace_back(e0, e1);
+        if (!rc) rc = rc2;
+    }
+    return rc;
 }
 
 // Generator over edges begin .. begin+count-1 writing edge pairs to `edges`;
@@ -792,6 +815,39 @@ const char *ba_strerror(int status)
 }
 
 int ba_last_hip_error(void) { return g_last_hip; }
+
+static void timing_release()
+{
+    for (auto &p : g_timing.ev) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    g_timing.ev.clear();
+}
+
+int ba_kernel_timing(int enable)
+{
+    timing_release();
+    g_timing.on = enable != 0;
+    return BA_OK;
+}
+
+int ba_kernel_timing_read(double *ms_total, uint64_t *launches)
+{
+    if (!ms_total || !launches) return BA_EINVAL;
+    double tot = 0.0;
+    int rc = BA_OK;
+    for (auto &p : g_timing.ev) {
+        float ms = 0.0f;
+        if (!rc) rc = hip_check(hipEventSynchronize(p.second));
+        if (!rc) rc = hip_check(hipEventElapsedTime(&ms, p.first, p.second));
+        tot += ms;
+    }
+    *ms_total = tot;
+    *launches = g_timing.ev.size();
+    timing_release();
+    return rc;
+}
 
 int ba_host_divide(uint32_t d, const uint64_t *x, uint64_t *q, uint64_t count)
 {
