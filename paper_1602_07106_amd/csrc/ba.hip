@@ -20,8 +20,9 @@
 // chains leave floor(r/2) (narrow path) or v (wide path) in a per-wave LDS
 // tile; when the tile is complete the wave writes it out as 16-byte
 // (two-edge) coalesced stores, computing u = floor(i/d) and v on the way.
-// The fused degree histogram adds one per second endpoint with a global
-// atomic (first endpoints contribute exactly d per node, in closed form).
+// The degree array (ba_degree.h) is computed from the written edges by a
+// radix partition and LDS histograms; first endpoints contribute exactly d
+// per node, in closed form.
 //
 // The streaming kernel (paper Section 3) stores nothing: each finished edge
 // updates the degree counts of the first k nodes (an LDS-privatised table for
@@ -47,14 +48,6 @@ constexpr int kGenBlock = 256;  // 4 waves
 constexpr int kGenWaves = kGenBlock / kWave;
 constexpr uint32_t kTile = 2048;  // edges per wave tile (8 KiB of LDS per wave)
 
-// Coarse (L1) partition of second endpoints for the degree pipeline.
-struct L1Args {
-    uint32_t S1, NB1;
-    uint64_t *cnt1;   // NB1 list fill counters
-    uint32_t *list;   // L1 storage
-    uint64_t off1[kMaxNB1], cap1[kMaxNB1];
-};
-
 struct GenArgs {
     HashKey key;
     Divider div;
@@ -63,8 +56,7 @@ struct GenArgs {
     uint64_t ntiles;  // ceil(count / kTile)
     uint32_t d;
     uint32_t *edges;  // 2*count uint32
-    uint32_t *deg;    // degree array (partition mode: overflow fallback)
-    L1Args l1;
+    uint32_t *vlist;  // count uint32 second endpoints (degree pipeline), or null
 };
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
@@ -73,40 +65,57 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-__device__ __forceinline__ void deg_add(uint32_t *deg, uint32_t v)
+
+// Edge pair j, j+1 of a tile from the stage: u = floor(i/d) and v (the
+// stage holds floor(r/2) on the narrow path, v itself on the wide path).
+template <bool NARROW>
+__device__ __forceinline__ void flush_pair(const GenArgs &a, const uint32_t *stage, uint64_t ibase, uint32_t j,
+                                           uint32_t &u0, uint32_t &u1, uint32_t &v0, uint32_t &v1)
 {
-    __hip_atomic_fetch_add(deg + v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint2 s = *reinterpret_cast<const uint2 *>(stage + j);
+    if constexpr (NARROW) {
+        const uint32_t i0 = (uint32_t)ibase + j;
+        u0 = div32(i0, a.div);
+        u1 = div32(i0 + 1, a.div);
+        v0 = div32(s.x, a.div);
+        v1 = div32(s.y, a.div);
+    } else {
+        const uint64_t i0 = ibase + j;
+        u0 = (uint32_t)div64(i0, a.div);
+        u1 = (uint32_t)div64(i0 + 1, a.div);
+        v0 = s.x;
+        v1 = s.y;
+    }
+}
+
+// Edges j and j+1 (when j+1 < tn) to the output, one 16-byte store when aligned.
+template <bool VEC16>
+__device__ __forceinline__ void store_pair(uint32_t *out, uint32_t j, uint32_t tn, uint32_t u0, uint32_t v0,
+                                           uint32_t u1, uint32_t v1)
+{
+    const bool two = j + 1 < tn;
+    if (VEC16 && two) {
+        *reinterpret_cast<uint4 *>(out + 2 * j) = make_uint4(u0, v0, u1, v1);
+    } else {
+        out[2 * j] = u0;
+        out[2 * j + 1] = v0;
+        if (two) {
+            out[2 * j + 2] = u1;
+            out[2 * j + 3] = v1;
+        }
+    }
 }
 
 // One chain step for every lane, then refill of the lanes that finished.
-// NARROW: all positions of the launch are below 2^32.  PART: also partition
-// the tile's second endpoints into the L1 lists of the degree pipeline.
-template <bool NARROW, bool PART, bool VEC16>
+// NARROW: all positions of the launch are below 2^32.
+template <bool NARROW, bool VEC16, bool VLIST>
 __global__ __launch_bounds__(kGenBlock) void k_gen_u32(GenArgs a)
 {
     __shared__ uint32_t stage_all[kGenWaves][kTile];
-    __shared__ uint16_t idx_all[PART ? kGenWaves : 1][PART ? kTile : 1];
-    // L1 tables, per wave: histogram and cursors split four ways (by lane & 3)
-    // so lanes of one bucket spread over four LDS words; per bucket the list
-    // slot of tile entry k is base + k while k < limit.
-    __shared__ uint32_t hist_all[PART ? kGenWaves : 1][PART ? 4 * kMaxNB1 : 1];
-    __shared__ uint32_t cur_all[PART ? kGenWaves : 1][PART ? 4 * kMaxNB1 : 1];
-    __shared__ uint64_t base_all[PART ? kGenWaves : 1][PART ? kMaxNB1 : 1];
-    __shared__ uint32_t limit_all[PART ? kGenWaves : 1][PART ? kMaxNB1 : 1];
-    __shared__ uint64_t off1[kMaxNB1], cap1[kMaxNB1];
     const uint32_t lane = __lane_id();
     const uint32_t wv = threadIdx.x / kWave;
     uint32_t *stage = stage_all[wv];
     const uint64_t wstride = (uint64_t)gridDim.x * kGenWaves;
-    if constexpr (PART) {
-        if (threadIdx.x < kMaxNB1) {
-            off1[threadIdx.x] = a.l1.off1[threadIdx.x];
-            cap1[threadIdx.x] = a.l1.cap1[threadIdx.x];
-        }
-        hist_all[wv][lane] = 0;
-        hist_all[wv][lane + kWave] = 0;
-        __syncthreads();
-    }
 
     for (uint64_t tile = (uint64_t)blockIdx.x * kGenWaves + wv; tile < a.ntiles; tile += wstride) {
         const uint64_t off = tile * kTile;
@@ -156,106 +165,16 @@ __global__ __launch_bounds__(kGenBlock) void k_gen_u32(GenArgs a)
 
         // Flush: two edges per lane per step, 16-byte stores.
         uint32_t *out = a.edges + 2 * off;
-        uint32_t *hist = hist_all[wv];
         for (uint32_t j = 2 * lane; j < tn; j += 2 * kWave) {
-            const uint2 s = *reinterpret_cast<const uint2 *>(stage + j);
             uint32_t u0, u1, v0, v1;
-            if constexpr (NARROW) {
-                const uint32_t i0 = (uint32_t)ibase + j;
-                u0 = div32(i0, a.div);
-                u1 = div32(i0 + 1, a.div);
-                v0 = div32(s.x, a.div);
-                v1 = div32(s.y, a.div);
-            } else {
-                const uint64_t i0 = ibase + j;
-                u0 = (uint32_t)div64(i0, a.div);
-                u1 = (uint32_t)div64(i0 + 1, a.div);
-                v0 = s.x;
-                v1 = s.y;
-            }
-            const bool two = j + 1 < tn;
-            if (VEC16 && two) {
-                *reinterpret_cast<uint4 *>(out + 2 * j) = make_uint4(u0, v0, u1, v1);
-            } else {
-                out[2 * j] = u0;
-                out[2 * j + 1] = v0;
-                if (two) {
-                    out[2 * j + 2] = u1;
-                    out[2 * j + 3] = v1;
-                }
-            }
-            if constexpr (PART) {
-                if constexpr (NARROW) *reinterpret_cast<uint2 *>(stage + j) = make_uint2(v0, v1);
-                atomicAdd(&hist[4 * (v0 >> a.l1.S1) + (lane & 3)], 1u);
-                if (two) atomicAdd(&hist[4 * (v1 >> a.l1.S1) + (lane & 3)], 1u);
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-        if constexpr (PART) {
-            // Counting sort of the tile's second endpoints by L1 bucket, one
-            // reservation per non-empty bucket, then runs appended in order.
-            uint32_t *cur = cur_all[wv], *limit = limit_all[wv];
-            uint64_t *base = base_all[wv];
-            uint16_t *idx = idx_all[wv];
-            const uint32_t S1 = a.l1.S1;
-            uint32_t h4[4] = {0, 0, 0, 0};
-            if (lane < a.l1.NB1) {
-                const uint4 hv = *reinterpret_cast<const uint4 *>(hist + 4 * lane);
-                h4[0] = hv.x, h4[1] = hv.y, h4[2] = hv.z, h4[3] = hv.w;
-            }
-            const uint32_t c = h4[0] + h4[1] + h4[2] + h4[3];
-            uint32_t incl = c;
-            for (int o = 1; o < kWave; o <<= 1) {
-                const uint32_t y = __shfl_up(incl, o);
-                if (lane >= (uint32_t)o) incl += y;
-            }
-            uint64_t g = 0;
-            const uint32_t stripe = (uint32_t)((blockIdx.x * kGenWaves + wv) % kStripes);
-            if (c)
-                g = atomicAdd((unsigned long long *)(a.l1.cnt1 + lane * kStripes + stripe),
-                              (unsigned long long)c);
-            if (lane < a.l1.NB1) {
-                const uint32_t st = incl - c;
-                cur[4 * lane] = st;
-                cur[4 * lane + 1] = st + h4[0];
-                cur[4 * lane + 2] = st + h4[0] + h4[1];
-                cur[4 * lane + 3] = st + h4[0] + h4[1] + h4[2];
-                const uint64_t room = g < cap1[lane] ? cap1[lane] - g : 0;
-                base[lane] = off1[lane] + stripe * cap1[lane] + g - st;
-                limit[lane] = (uint32_t)min((uint64_t)st + room, (uint64_t)kTile);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            hist[lane] = 0;
-            hist[lane + kWave] = 0;
-            // each lane scatters the entries it stored in the edge flush
-            // (positions 2*lane + 128*t and +1), so the sort order within a
-            // bucket follows the lane's sub-cursor
-            for (uint32_t j = 2 * lane; j < tn; j += 2 * kWave) {
-                const uint2 vv = *reinterpret_cast<const uint2 *>(stage + j);
-                const uint32_t s0 = atomicAdd(&cur[4 * (vv.x >> S1) + (lane & 3)], 1u);
-                idx[s0] = (uint16_t)j;
-                if (j + 1 < tn) {
-                    const uint32_t s1 = atomicAdd(&cur[4 * (vv.y >> S1) + (lane & 3)], 1u);
-                    idx[s1] = (uint16_t)(j + 1);
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const uint32_t mask1 = (S1 >= 32) ? 0xFFFFFFFFu : ((1u << S1) - 1u);
-#pragma unroll 4
-            for (uint32_t k = lane; k < tn; k += kWave) {
-                const uint32_t v = stage[idx[k]];
-                const uint32_t b = v >> S1;
-                if (k < limit[b])
-                    a.l1.list[base[b] + k] = v & mask1;
+            flush_pair<NARROW>(a, stage, ibase, j, u0, u1, v0, v1);
+            store_pair<VEC16>(out, j, tn, u0, v0, u1, v1);
+            if constexpr (VLIST) {
+                // second endpoints alone, for the degree pipeline (8-byte aligned: j, off even)
+                if (j + 1 < tn)
+                    *reinterpret_cast<uint2 *>(a.vlist + off + j) = make_uint2(v0, v1);
                 else
-                    deg_add(a.deg, v);
+                    a.vlist[off + j] = v0;
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -464,11 +383,11 @@ struct KernelTiming {
 };
 static thread_local KernelTiming g_timing;
 
-template <bool N, bool D, bool V>
+template <bool N, bool V, bool L>
 static int launch_gen_one(const GenArgs &a, hipStream_t st)
 {
     uint32_t grid = 0;
-    int rc = persistent_grid(k_gen_u32<N, D, V>, kGenBlock, &grid);
+    int rc = persistent_grid(k_gen_u32<N, V, L>, kGenBlock, &grid);
     if (rc) return rc;
     grid = grid_for(a.ntiles, kGenWaves, grid);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -477,7 +396,7 @@ static int launch_gen_one(const GenArgs &a, hipStream_t st)
         if ((rc = hip_check(hipEventCreate(&e1)))) return rc;
         if ((rc = hip_check(hipEventRecord(e0, st)))) return rc;
     }
-    hipLaunchKernelGGL((k_gen_u32<N, D, V>), dim3(grid), dim3(kGenBlock), 0, st, a);
+    hipLaunchKernelGGL((k_gen_u32<N, V, L>), dim3(grid), dim3(kGenBlock), 0, st, a);
     rc = hip_check(hipGetLastError());
     if (g_timing.on) {
         const int rc2 = hip_check(hipEventRecord(e1, st));
@@ -487,10 +406,10 @@ static int launch_gen_one(const GenArgs &a, hipStream_t st)
     return rc;
 }
 
-// Generator over edges begin .. begin+count-1 writing edge pairs to `edges`;
-// with `l1` set, also the L1 partition of the degree pipeline.
+// Generator over edges begin .. begin+count-1 writing edge pairs to `edges`
+// and, when vlist is set (8-byte aligned), the second endpoints alone.
 static int launch_gen_u32(uint64_t begin, uint64_t count, uint32_t d, uint64_t seed, uint32_t *edges,
-                          uint32_t *deg, const L1Args *l1, hipStream_t st)
+                          hipStream_t st, uint32_t *vlist = nullptr)
 {
     if (count == 0) return BA_OK;
     GenArgs a{};
@@ -501,11 +420,10 @@ static int launch_gen_u32(uint64_t begin, uint64_t count, uint32_t d, uint64_t s
     a.ntiles = (count + kTile - 1) / kTile;
     a.d = d;
     a.edges = edges;
-    a.deg = deg;
-    if (l1) a.l1 = *l1;
+    a.vlist = vlist;
     const bool narrow = 2 * (begin + count) <= ((uint64_t)1 << 32);
     const bool vec16 = ((uintptr_t)edges & 15) == 0;
-    const int sel = (narrow ? 4 : 0) | (l1 ? 2 : 0) | (vec16 ? 1 : 0);
+    const int sel = (narrow ? 4 : 0) | (vec16 ? 2 : 0) | (vlist ? 1 : 0);
     switch (sel) {
     case 7: return launch_gen_one<true, true, true>(a, st);
     case 6: return launch_gen_one<true, true, false>(a, st);
@@ -518,8 +436,8 @@ static int launch_gen_u32(uint64_t begin, uint64_t count, uint32_t d, uint64_t s
     }
 }
 
-// Capacity scale of the L1 lists (1 normally); BA_DEG_CAP_SCALE < 1 forces
-// the overflow path, for tests.
+// Capacity scale of the partition regions (1 normally); BA_DEG_CAP_SCALE < 1
+// forces the overflow path, for tests.
 static double deg_cap_scale()
 {
     const char *e = getenv("BA_DEG_CAP_SCALE");
@@ -528,11 +446,12 @@ static double deg_cap_scale()
     return (x > 0.0 && x <= 1.0) ? x : 1.0;
 }
 
-// Largest pass (edges) of the degree pipeline that fits ws_bytes, 0 if none.
+// Largest pass (edges) of the degree pipeline whose layout for up to
+// kPBlocksMax partition blocks fits ws_bytes; 0 if none.
 static uint64_t deg_piece(uint64_t n, uint64_t count, uint64_t ws_bytes)
 {
     uint64_t piece = count < kPieceMax ? count : kPieceMax;
-    while (piece > 0 && make_deg_plan(n, piece, kTile).bytes > ws_bytes) {
+    while (piece > 0 && make_deg_plan(n, piece, kPBlocksMax).bytes > ws_bytes) {
         if (piece <= kPieceMin) return 0;
         piece /= 2;
         if (piece < kPieceMin) piece = kPieceMin;
@@ -540,51 +459,56 @@ static uint64_t deg_piece(uint64_t n, uint64_t count, uint64_t ws_bytes)
     return piece;
 }
 
+// Second endpoints of edges begin .. begin+count-1 (the target list the
+// generator left in the workspace) added to deg: partition, totals, part
+// scan, histograms.  First endpoints are the caller's (a fill of d or the
+// closed-form range counts).
+static int degrees_of_targets(uint64_t n, uint32_t d, uint64_t begin, uint64_t count, uint32_t *deg, void *ws,
+                              hipStream_t st)
+{
+    uint32_t P = 0;
+    int rc = persistent_grid(k_deg_part, kPBlock, &P);
+    if (rc) return rc;
+    if (P > kPBlocksMax) P = kPBlocksMax;
+    DegArgs a{};
+    a.p = make_deg_plan(n, count, P);
+    a.B = begin;
+    a.d = d;
+    a.deg = deg;
+    a.ws = (unsigned char *)ws;
+    a.scale = deg_cap_scale();
+    hipLaunchKernelGGL(k_deg_plan, dim3(1), dim3(1024), 0, st, a);
+    if ((rc = hip_check(hipGetLastError()))) return rc;
+    for (uint32_t w = 0; w < a.p.NW; w++) {
+        a.g0 = w * kWin;
+        hipLaunchKernelGGL(k_deg_part, dim3(P), dim3(kPBlock), 0, st, a);
+        if ((rc = hip_check(hipGetLastError()))) return rc;
+    }
+    hipLaunchKernelGGL(k_deg_tot, dim3(a.p.NBsub), dim3(256), 0, st, a);
+    if ((rc = hip_check(hipGetLastError()))) return rc;
+    hipLaunchKernelGGL(k_deg_scan, dim3(1), dim3(1024), 0, st, a);
+    if ((rc = hip_check(hipGetLastError()))) return rc;
+    const uint64_t parts_max = (uint64_t)a.p.NBsub + (count + kHPart - 1) / kHPart + 1;
+    hipLaunchKernelGGL(k_deg_hist, dim3((uint32_t)parts_max), dim3(kHBlock), 0, st, a);
+    return hip_check(hipGetLastError());
+}
+
 // Edges [begin, begin+count) written to `edges`, their second endpoints
-// added to deg through the partition pipeline (first endpoints are the
-// caller's: a fill of d or the closed-form range counts).
+// added to deg, pass by pass.
 static int gen_with_degrees(uint64_t n, uint32_t d, uint64_t seed, uint64_t begin, uint64_t count,
                             uint32_t *edges, uint32_t *deg, void *ws, uint64_t ws_bytes, hipStream_t st)
 {
     if (count == 0) return BA_OK;
     const uint64_t piece = deg_piece(n, count, ws_bytes);
     if (piece == 0 || !ws || ((uintptr_t)ws & 255)) return BA_EINVAL;
-    const double scale = deg_cap_scale();
     for (uint64_t done = 0; done < count; done += piece) {
-        const uint64_t B = begin + done;
         const uint64_t C = count - done < piece ? count - done : piece;
-        DegArgs da{};
-        da.p = make_deg_plan(n, C, kTile);
-        da.c = make_deg_caps(da.p, n, d, B, C, kTile, scale);
-        da.n = n;
-        da.deg = deg;
-        da.ws = (unsigned char *)ws;
-        L1Args l1{};
-        l1.S1 = da.p.S1;
-        l1.NB1 = da.p.NB1;
-        l1.cnt1 = (uint64_t *)(da.ws + da.p.o_cnt1);
-        l1.list = (uint32_t *)(da.ws + da.p.o_L1);
-        for (uint32_t b = 0; b < kMaxNB1; b++) {
-            l1.off1[b] = da.c.off1[b];
-            l1.cap1[b] = da.c.cap1[b];
-        }
-        hipLaunchKernelGGL(k_deg_zero, dim3(1), dim3(256), 0, st, da);
-        int rc = hip_check(hipGetLastError());
+        const DegPlan p = make_deg_plan(n, C, kPBlocksMax);
+        int rc = launch_gen_u32(begin + done, C, d, seed, edges + 2 * done, st,
+                                (uint32_t *)((unsigned char *)ws + p.o_V));
         if (rc) return rc;
-        hipLaunchKernelGGL(k_deg_plan2, dim3((da.p.NBsub + 255) / 256), dim3(256), 0, st, da);
-        if ((rc = hip_check(hipGetLastError()))) return rc;
-        hipLaunchKernelGGL(k_deg_off2, dim3(1), dim3(1024), 0, st, da);
-        if ((rc = hip_check(hipGetLastError()))) return rc;
-        rc = launch_gen_u32(B, C, d, seed, edges + 2 * done, deg, &l1, st);
+        rc = degrees_of_targets(n, d, begin + done, C, deg, ws, st);
         if (rc) return rc;
-        const size_t h2_lds = (sizeof(uint64_t) + 4 * sizeof(uint32_t)) * da.p.NB2 + sizeof(uint32_t) * kH2Chunk;
-        hipLaunchKernelGGL(k_deg_h2, dim3(da.c.capch[da.p.NB1]), dim3(kH2Block), h2_lds, st, da);
-        if ((rc = hip_check(hipGetLastError()))) return rc;
-        hipLaunchKernelGGL(k_deg_h2c, dim3(1), dim3(1024), 0, st, da);
-        if ((rc = hip_check(hipGetLastError()))) return rc;
-        const uint64_t h3_grid = (uint64_t)da.p.NBsub + (C + kH3Part - 1) / kH3Part + 1;
-        hipLaunchKernelGGL(k_deg_h3, dim3((uint32_t)h3_grid), dim3(kH3Block), 0, st, da);
-        if ((rc = hip_check(hipGetLastError()))) return rc;
     }
     return BA_OK;
 }
@@ -595,7 +519,7 @@ static int gen_with_degrees_alloc(uint64_t n, uint32_t d, uint64_t seed, uint64_
 {
     if (count == 0) return BA_OK;
     const uint64_t piece = count < kPieceMax ? count : kPieceMax;
-    const uint64_t bytes = make_deg_plan(n, piece, kTile).bytes;
+    const uint64_t bytes = make_deg_plan(n, piece, kPBlocksMax).bytes;
     void *ws = nullptr;
     int rc = hip_check(hipMallocAsync(&ws, bytes, st));
     if (rc) return rc;
@@ -686,7 +610,7 @@ int ba_generate(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint32_t
     hipStream_t st = (hipStream_t)stream;
     if ((rc = fill_first_endpoints_whole(n, d, deg, st))) return rc;
     if (deg) return gen_with_degrees_alloc(n, d, seed, 0, m, edges, deg, st);
-    return launch_gen_u32(0, m, d, seed, edges, nullptr, nullptr, st);
+    return launch_gen_u32(0, m, d, seed, edges, st);
 }
 
 int ba_generate_ws(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint32_t *deg, void *workspace,
@@ -702,7 +626,7 @@ int ba_generate_ws(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint3
     hipStream_t st = (hipStream_t)stream;
     if ((rc = fill_first_endpoints_whole(n, d, deg, st))) return rc;
     if (deg) return gen_with_degrees(n, d, seed, 0, m, edges, deg, workspace, workspace_bytes, st);
-    return launch_gen_u32(0, m, d, seed, edges, nullptr, nullptr, st);
+    return launch_gen_u32(0, m, d, seed, edges, st);
 }
 
 int ba_generate_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin, uint64_t edge_count,
@@ -715,7 +639,7 @@ int ba_generate_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin
         if ((rc = launch_first_endpoints<uint32_t>(deg, n, edge_begin, edge_count, d, n, st))) return rc;
         return gen_with_degrees_alloc(n, d, seed, edge_begin, edge_count, edges, deg, st);
     }
-    return launch_gen_u32(edge_begin, edge_count, d, seed, edges, nullptr, nullptr, st);
+    return launch_gen_u32(edge_begin, edge_count, d, seed, edges, st);
 }
 
 int ba_generate_range_ws(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin, uint64_t edge_count,
@@ -732,7 +656,7 @@ int ba_generate_range_ws(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_be
         if ((rc = launch_first_endpoints<uint32_t>(deg, n, edge_begin, edge_count, d, n, st))) return rc;
         return gen_with_degrees(n, d, seed, edge_begin, edge_count, edges, deg, workspace, workspace_bytes, st);
     }
-    return launch_gen_u32(edge_begin, edge_count, d, seed, edges, nullptr, nullptr, st);
+    return launch_gen_u32(edge_begin, edge_count, d, seed, edges, st);
 }
 
 uint64_t ba_generate_workspace_bytes(uint64_t n, uint32_t d, uint64_t edge_count)
@@ -740,7 +664,7 @@ uint64_t ba_generate_workspace_bytes(uint64_t n, uint32_t d, uint64_t edge_count
     uint64_t m;
     if (!graph_fits(n, d, &m) || edge_count == 0) return 0;
     const uint64_t piece = edge_count < kPieceMax ? edge_count : kPieceMax;
-    return make_deg_plan(n, piece, kTile).bytes;
+    return make_deg_plan(n, piece, kPBlocksMax).bytes;
 }
 
 int ba_generate_range_u64(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin, uint64_t edge_count,

@@ -1,33 +1,36 @@
 // ba_degree.h -- full degree array of a generated graph on gfx950.
 //
 // deg[v] counts the positions of the edge array holding v (paper Section 2:
-// E[2i] = floor(i/d) gives every node exactly d first endpoints, the rest are
+// E[2i] = floor(i/d) gives every node exactly d first endpoints; the rest are
 // the second endpoints v_i).  Second endpoints land on random nodes, heavily
 // skewed towards low IDs (E[deg v] ~ d*sqrt(n/v)).  Per-edge global atomics
 // on gfx950 run at a fixed ~2.7e10 cache-line requests/s whatever the
 // footprint, about 15x slower than generating the edges, so the counts go
-// through a two-level radix partition in HBM and finish as LDS histograms:
+// through a radix partition in HBM and finish as LDS histograms:
 //
-//   L1 (fused into the generator's tile flush): each wave counting-sorts the
-//      second endpoints of its 2048-edge tile by the high bits v >> S1 (at
-//      most 32 coarse buckets) and appends each bucket's run to that bucket's
-//      list with one reservation per (tile, bucket).  Every bucket list is
-//      striped 16 ways by wave: one fill counter per bucket would take an
-//      atomic from every tile of the launch and serialise them.
-//   H2: blocks take 8192-entry chunks of an L1 list, counting-sort them into
-//      32768-node sub-buckets and append each run of 16-bit local indices to
-//      its sub-bucket's list (one reservation per (chunk, sub-bucket)).
-//   H2c: number of count parts (2^20 entries each) per sub-bucket, scanned.
-//   H3: one block per part streams its slice of a sub-bucket list into an
-//      LDS histogram of 32768 counters and adds the counts to deg (plain
+//   V  (in the generator): the tile flush also writes the second endpoints
+//      alone, 4 bytes per edge, so the partition reads half the bytes of the
+//      edge array.
+//   P  (k_deg_part): persistent blocks read that list in 24K-edge
+//      chunks, counting-sort the second endpoints of a chunk by 32768-node
+//      sub-bucket (v >> 15) in LDS and append each sub-bucket's run of 16-bit
+//      local indices to the block's own region for that sub-bucket.  Regions
+//      are private per (block, sub-bucket), so no reservation atomics; a
+//      block keeps its fill counters in LDS across its chunks.  At most 2048
+//      sub-buckets fit the LDS tables, so larger graphs take several windows
+//      of sub-buckets, each a pass over the edges.
+//   T  (k_deg_tot): per sub-bucket, its entry total over all regions and its
+//      number of count parts (about 2^20 entries each).
+//   S  (k_deg_scan): exclusive scan of the parts.
+//   H  (k_deg_hist): one block per part streams its regions into an LDS
+//      histogram of 32768 counters and adds the counts to deg (plain
 //      read-modify-write when a sub-bucket is a single part, atomics only for
 //      the few heavy multi-part ones).
 //
-// List capacities (L1 on the host, L2 on the device) come from the
-// mean-field Barabasi-Albert degree law (expected second endpoints of edges
-// [B, B+C) on nodes [a, b)) with slack; anything beyond a capacity falls back
-// to a direct global atomic, so the result never depends on the capacities,
-// only the speed does.
+// Region capacities come from the mean-field Barabasi-Albert degree law
+// (expected second endpoints of edges [B, B+C) on nodes [a, b)) with slack;
+// entries beyond a capacity fall back to a direct global atomic, so the
+// result never depends on the capacities, only the speed does.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,48 +39,19 @@
 
 namespace ba {
 
-constexpr uint32_t kS2 = 15;                  // sub-bucket width: 32768 nodes
+constexpr uint32_t kS2 = 15;                    // sub-bucket width: 32768 nodes
 constexpr uint32_t kSub = 1u << kS2;
-constexpr uint32_t kMaxNB1 = 32;              // coarse (L1) buckets
-constexpr uint32_t kStripes = 16;             // L1 sub-lists per bucket
-constexpr uint32_t kH2Chunk = 8192;           // entries per H2 block
-constexpr uint32_t kH2Block = 256;
-constexpr uint32_t kH3Part = 1u << 20;        // entries per H3 part
-constexpr uint32_t kH3Block = 1024;
-constexpr uint64_t kPieceMax = 1ull << 31;    // edges per pipeline pass
+constexpr uint32_t kWin = 2048;                 // sub-buckets per partition window
+constexpr uint32_t kPBlock = 1024;
+constexpr uint32_t kPPer = 24;                  // edges per thread per chunk
+constexpr uint32_t kPChunk = kPBlock * kPPer;   // 24576 edges per chunk
+constexpr uint32_t kPBlocksMax = 1024;          // partition blocks a layout allows
+constexpr uint32_t kHPart = 1u << 20;           // entries per count part (target)
+constexpr uint32_t kHBlock = 1024;
+constexpr uint64_t kPieceMax = 1ull << 31;      // edges per pipeline pass
 constexpr uint64_t kPieceMin = 1ull << 20;
 
-// Layout of one pass of the pipeline over C edges of a graph with n nodes.
-struct DegPlan {
-    uint32_t S1, NB1, NB2, NBsub;
-    uint64_t C;                       // edges of this pass (capacity)
-    uint64_t A1;                      // L1 entries reserved in the layout
-    uint64_t A2;                      // L2 entries reserved in the layout
-    // workspace byte offsets
-    uint64_t o_cnt1, o_L1, o_cnt2, o_cap2, o_off2, o_L2, o_parts, o_partoff, bytes;
-};
-
-// Per-pass bucket capacities (depend on where the pass starts).  Stripe q
-// of bucket b is the list at off1[b] + q * cap1[b] holding up to cap1[b].
-struct DegCaps {
-    uint64_t cap1[kMaxNB1];    // per stripe
-    uint64_t off1[kMaxNB1];    // entry offset of each bucket's stripes
-    uint32_t chs[kMaxNB1];     // H2 chunks per stripe: ceil(cap1 / kH2Chunk)
-    uint32_t capch[kMaxNB1 + 1];  // prefix over buckets of kStripes * chs
-    uint64_t B;                // first edge of the pass
-    uint64_t d;
-};
-
-static inline uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
-
-static inline uint32_t ceil_log2_u64(uint64_t x)
-{
-    uint32_t l = 0;
-    while (l < 64 && ((uint64_t)1 << l) < x) l++;
-    return l;
-}
-
-static inline uint64_t isqrt_u64(uint64_t x)
+__host__ __device__ inline uint64_t isqrt_u64(uint64_t x)
 {
     uint64_t r = (uint64_t)sqrt((double)x);
     while (r * r > x) r--;
@@ -106,113 +80,84 @@ __host__ __device__ inline double expected_bucket_mass(uint64_t d, uint64_t B, u
     return (double)d * (G[1] - G[0]);
 }
 
-static inline DegPlan make_deg_plan(uint64_t n, uint64_t C, uint32_t tile)
+// Capacity of one (block, sub-bucket) region when P blocks share an expected
+// mass M: an even share plus slack.
+__host__ __device__ inline uint32_t region_cap(double M, uint32_t P)
+{
+    const double e = M / (double)P;
+    return (uint32_t)(1.15 * e + 8.0 * sqrt(e) + 64.0);
+}
+
+// Layout of one pass of the pipeline over C edges of a graph with n nodes
+// partitioned by at most P blocks.
+struct DegPlan {
+    uint32_t NBsub, NW, P;
+    uint64_t n, C;
+    uint64_t A;  // region entries reserved in the layout
+    uint64_t o_V, o_rcap, o_off, o_fill, o_tot, o_parts, o_partoff, o_L, bytes;
+};
+
+static inline uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
+
+static inline DegPlan make_deg_plan(uint64_t n, uint64_t C, uint32_t P)
 {
     DegPlan p{};
-    const uint32_t lg = ceil_log2_u64(n < 2 ? 2 : n);
-    p.S1 = lg > kS2 + 5 ? lg - 5 : kS2;
-    p.NB1 = (uint32_t)((n + ((uint64_t)1 << p.S1) - 1) >> p.S1);
-    if (p.NB1 == 0) p.NB1 = 1;
-    p.NB2 = 1u << (p.S1 - kS2);
+    p.n = n;
+    p.C = C;
+    p.P = P;
     p.NBsub = (uint32_t)((n + kSub - 1) >> kS2);
     if (p.NBsub == 0) p.NBsub = 1;
-    p.C = C;
-    // a list set's capacities sum to at most 1.15 C + 16 sqrt(N C) + N margin
-    p.A1 = C + C / 6 + 16 * isqrt_u64((uint64_t)p.NB1 * C) + 16 + (uint64_t)p.NB1 * (2 * tile + 4097) +
-           (uint64_t)p.NB1 * kStripes * (2 * tile + 1);
-    p.A2 = C + C / 6 + 16 * isqrt_u64((uint64_t)p.NBsub * C) + 16 + (uint64_t)p.NBsub * (2 * kH2Chunk + 1025);
+    p.NW = (p.NBsub + kWin - 1) / kWin;
+    // sum of region_cap over sub-buckets and blocks is at most
+    //   1.15 C + 8 sqrt(P NBsub C) + 64 P NBsub  (Cauchy-Schwarz), plus rounding
+    p.A = C + C / 6 + 8 * isqrt_u64((uint64_t)P * p.NBsub * C) + 8 + 65ull * P * p.NBsub;
     uint64_t o = 0;
-    p.o_cnt1 = o; o = align256(o + 8 * kMaxNB1 * kStripes);
-    p.o_L1 = o; o = align256(o + 4 * p.A1);
-    p.o_cnt2 = o; o = align256(o + 4 * (uint64_t)p.NBsub);
-    p.o_cap2 = o; o = align256(o + 4 * (uint64_t)p.NBsub);
-    p.o_off2 = o; o = align256(o + 8 * (uint64_t)p.NBsub);
-    p.o_L2 = o; o = align256(o + 2 * p.A2);
-    p.o_parts = o; o = align256(o + 4 * (uint64_t)p.NBsub);
-    p.o_partoff = o; o = align256(o + 4 * ((uint64_t)p.NBsub + 1));
+    p.o_V = o; o = align256(o + 4 * C);
+    p.o_rcap = o; o = align256(o + 4ull * p.NBsub);
+    p.o_off = o; o = align256(o + 8ull * p.NBsub);
+    p.o_fill = o; o = align256(o + 4ull * P * p.NBsub);
+    p.o_tot = o; o = align256(o + 4ull * p.NBsub);
+    p.o_parts = o; o = align256(o + 4ull * p.NBsub);
+    p.o_partoff = o; o = align256(o + 4ull * (p.NBsub + 1));
+    p.o_L = o; o = align256(o + 2 * p.A);
     p.bytes = o;
     return p;
 }
 
-// Capacities for the pass over edges [B, B+C); `scale` (normally 1) shrinks
-// them for tests of the overflow path.
-static inline DegCaps make_deg_caps(const DegPlan &p, uint64_t n, uint64_t d, uint64_t B, uint64_t C,
-                                    uint32_t tile, double scale)
-{
-    DegCaps c{};
-    uint64_t off = 0;
-    c.capch[0] = 0;
-    for (uint32_t b = 0; b < p.NB1; b++) {
-        uint64_t cap;
-        if (p.NB1 == 1) {
-            cap = C;
-        } else {
-            const double lo = (double)((uint64_t)b << p.S1);
-            const double hi = (double)(((uint64_t)(b + 1) << p.S1) < n ? ((uint64_t)(b + 1) << p.S1) : n);
-            const double M = expected_bucket_mass(d, B, C, lo, hi);
-            cap = (uint64_t)(1.15 * M) + 16 * isqrt_u64((uint64_t)M) + 2 * tile + 4096;
-            if (cap > C) cap = C;
-        }
-        // per stripe: an even share plus one tile of slack either way
-        uint64_t cs = (uint64_t)((double)(cap / kStripes + 2 * tile) * scale);
-        if (off + kStripes * cs > p.A1) cs = (p.A1 - off) / kStripes;  // never past the layout
-        c.cap1[b] = cs;
-        c.off1[b] = off;
-        off += kStripes * cs;
-        c.chs[b] = (uint32_t)((cs + kH2Chunk - 1) / kH2Chunk);
-        c.capch[b + 1] = c.capch[b] + kStripes * c.chs[b];
-    }
-    c.B = B;
-    c.d = d;
-    return c;
-}
-
 struct DegArgs {
     DegPlan p;
-    DegCaps c;
-    uint64_t n;
+    uint64_t B, d;          // first edge of the pass, edges per node
     uint32_t *deg;
     unsigned char *ws;
+    uint32_t g0;            // first sub-bucket of the window (partition kernel)
+    double scale;           // capacity scale (1 normally)
 };
 
-__device__ __forceinline__ uint64_t *ws_cnt1(const DegArgs &a) { return (uint64_t *)(a.ws + a.p.o_cnt1); }
-__host__ __device__ inline uint64_t *ws_cnt1_ptr(unsigned char *ws, const DegPlan &p) { return (uint64_t *)(ws + p.o_cnt1); }
-__device__ __forceinline__ uint32_t *ws_L1(const DegArgs &a) { return (uint32_t *)(a.ws + a.p.o_L1); }
-__device__ __forceinline__ uint32_t *ws_cnt2(const DegArgs &a) { return (uint32_t *)(a.ws + a.p.o_cnt2); }
-__device__ __forceinline__ uint32_t *ws_cap2(const DegArgs &a) { return (uint32_t *)(a.ws + a.p.o_cap2); }
-__device__ __forceinline__ uint64_t *ws_off2(const DegArgs &a) { return (uint64_t *)(a.ws + a.p.o_off2); }
-__device__ __forceinline__ uint16_t *ws_L2(const DegArgs &a) { return (uint16_t *)(a.ws + a.p.o_L2); }
+__device__ __forceinline__ const uint32_t *ws_V(const DegArgs &a) { return (const uint32_t *)(a.ws + a.p.o_V); }
+__device__ __forceinline__ uint32_t *ws_rcap(const DegArgs &a) { return (uint32_t *)(a.ws + a.p.o_rcap); }
+__device__ __forceinline__ uint64_t *ws_off(const DegArgs &a) { return (uint64_t *)(a.ws + a.p.o_off); }
+__device__ __forceinline__ uint32_t *ws_fill(const DegArgs &a) { return (uint32_t *)(a.ws + a.p.o_fill); }
+__device__ __forceinline__ uint32_t *ws_tot(const DegArgs &a) { return (uint32_t *)(a.ws + a.p.o_tot); }
 __device__ __forceinline__ uint32_t *ws_parts(const DegArgs &a) { return (uint32_t *)(a.ws + a.p.o_parts); }
 __device__ __forceinline__ uint32_t *ws_partoff(const DegArgs &a) { return (uint32_t *)(a.ws + a.p.o_partoff); }
+__device__ __forceinline__ uint16_t *ws_L(const DegArgs &a) { return (uint16_t *)(a.ws + a.p.o_L); }
 
-// Entries actually stored in stripe q of L1 bucket b (the rest overflowed).
-__device__ __forceinline__ uint64_t l1_len(const DegArgs &a, uint32_t b, uint32_t q)
+__device__ __forceinline__ void deg_atomic_add(uint32_t *deg, uint64_t v, uint32_t c)
 {
-    const uint64_t c = ws_cnt1(a)[b * kStripes + q];
-    return c < a.c.cap1[b] ? c : a.c.cap1[b];
+    __hip_atomic_fetch_add(deg + v, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void k_deg_zero(DegArgs a)
+// Workgroup barrier that orders LDS only: global stores issued before it
+// stay in flight (a full __syncthreads would wait for them to complete).
+__device__ __forceinline__ void lds_barrier()
 {
-    for (uint32_t x = threadIdx.x; x < kMaxNB1 * kStripes; x += blockDim.x) ws_cnt1(a)[x] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Per sub-bucket L2 capacity from the degree law, zeroed fill counters.
-__global__ void k_deg_plan2(DegArgs a)
-{
-    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.p.NBsub) return;
-    const double lo = (double)((uint64_t)g << kS2);
-    const uint64_t hi_n = ((uint64_t)(g + 1) << kS2) < a.n ? ((uint64_t)(g + 1) << kS2) : a.n;
-    const double M = expected_bucket_mass(a.c.d, a.c.B, a.p.C, lo, (double)hi_n);
-    uint64_t cap = (uint64_t)(1.15 * M) + 16 * (uint64_t)sqrt(M) + 2 * kH2Chunk + 1024;
-    if (a.p.NBsub == 1 || cap > a.p.C) cap = a.p.C;
-    ws_cap2(a)[g] = (uint32_t)cap;
-    ws_cnt2(a)[g] = 0;
-}
-
-// Block-wide exclusive scan of one value per thread (any multiple of 64
-// threads up to 1024); `sh` holds 16 words.
+// Block-wide exclusive scan of one value per thread (blockDim.x a multiple
+// of 64, at most 1024); `sh` holds 16 words.
 template <class T>
 __device__ __forceinline__ T block_exclusive_scan(T x, T *sh, T *total)
 {
@@ -223,136 +168,169 @@ __device__ __forceinline__ T block_exclusive_scan(T x, T *sh, T *total)
         if (lane >= (uint32_t)o) incl += y;
     }
     if (lane == 63) sh[w] = incl;
-    __syncthreads();
+    lds_barrier();
     T base = 0, tot = 0;
     for (uint32_t q = 0; q < nw; q++) {
         if (q < w) base += sh[q];
         tot += sh[q];
     }
-    __syncthreads();
+    lds_barrier();
     *total = tot;
     return base + incl - x;
 }
 
-// Offsets of the L2 lists: exclusive scan of the capacities, clamped to the
-// layout (one block of 1024).
-__global__ __launch_bounds__(1024) void k_deg_off2(DegArgs a)
+// Region capacity of every sub-bucket (scaled for tests of the overflow
+// path) and the offset of each sub-bucket's P regions (one block).
+__global__ __launch_bounds__(1024) void k_deg_plan(DegArgs a)
 {
     __shared__ uint64_t sh[16];
     const uint32_t N = a.p.NBsub;
-    uint32_t *cap = ws_cap2(a);
-    uint64_t *off = ws_off2(a);
+    uint32_t *rcap = ws_rcap(a);
+    uint64_t *off = ws_off(a);
     uint64_t carry = 0;
     for (uint32_t i0 = 0; i0 < N; i0 += 1024) {
-        const uint32_t i = i0 + threadIdx.x;
-        const uint64_t x = i < N ? cap[i] : 0;
+        const uint32_t g = i0 + threadIdx.x;
+        uint64_t x = 0;
+        uint32_t cap = 0;
+        if (g < N) {
+            const double lo = (double)((uint64_t)g << kS2);
+            const uint64_t hi = ((uint64_t)(g + 1) << kS2) < a.p.n ? ((uint64_t)(g + 1) << kS2) : a.p.n;
+            const double M = N == 1 ? (double)a.p.C : expected_bucket_mass(a.d, a.B, a.p.C, lo, (double)hi);
+            cap = (uint32_t)((double)region_cap(M, a.p.P) * a.scale);
+            x = (uint64_t)cap * a.p.P;
+        }
         uint64_t tot;
         const uint64_t ex = block_exclusive_scan<uint64_t>(x, sh, &tot);
-        if (i < N) {
-            uint64_t o = carry + ex, c = x;
-            if (o > a.p.A2) o = a.p.A2;
-            if (o + c > a.p.A2) cap[i] = (uint32_t)(a.p.A2 - o);
-            off[i] = o;
+        if (g < N) {
+            uint64_t o = carry + ex;
+            if (o > a.p.A) o = a.p.A;
+            if (o + x > a.p.A) cap = (uint32_t)((a.p.A - o) / a.p.P);  // never past the layout
+            rcap[g] = cap;
+            off[g] = o;
         }
         carry += tot;
     }
 }
 
-// H2: one block per L1 chunk.  Dynamic LDS: cnt, start, cur, lim [NB2] u32,
-// dst [NB2] u64, out [kH2Chunk] u32.
-__global__ __launch_bounds__(kH2Block) void k_deg_h2(DegArgs a)
+// P: partition of second endpoints into per-(block, sub-bucket) regions,
+// for sub-buckets g0 .. g0+kWin-1.
+__global__ __launch_bounds__(kPBlock) void k_deg_part(DegArgs a)
 {
-    extern __shared__ uint64_t sm64[];
+    __shared__ uint32_t cnt[kWin], lim[kWin], fill[kWin];
+    __shared__ uint64_t dst[kWin];
+    __shared__ uint32_t stage[kPChunk];  // sorted (bin << 15 | local index)
     __shared__ uint32_t scan_sh[16];
-    const uint32_t NB2 = a.p.NB2;
-    uint64_t *dst = sm64;
-    uint32_t *cnt = (uint32_t *)(sm64 + NB2), *start = cnt + NB2, *cur = cnt + 2 * NB2, *lim = cnt + 3 * NB2;
-    uint32_t *out = cnt + 4 * NB2;
+    const uint32_t g0 = a.g0;
+    const uint32_t nwin = min(kWin, a.p.NBsub - g0);
+    const uint32_t blk = blockIdx.x, P = gridDim.x;
+    const uint32_t *rcap = ws_rcap(a);
+    const uint64_t *off = ws_off(a);
+    uint16_t *L = ws_L(a);
+    for (uint32_t b = threadIdx.x; b < kWin; b += kPBlock) fill[b] = 0;
 
-    const uint32_t k = blockIdx.x;
-    uint32_t b = 0;
-    while (b + 1 < a.p.NB1 && a.c.capch[b + 1] <= k) b++;
-    const uint32_t r = k - a.c.capch[b];
-    const uint32_t q = r / a.c.chs[b], j = r % a.c.chs[b];
-    const uint64_t nb = l1_len(a, b, q);
-    if ((uint64_t)j * kH2Chunk >= nb) return;
-    const uint32_t len = (uint32_t)min((uint64_t)kH2Chunk, nb - (uint64_t)j * kH2Chunk);
-    const uint32_t *src = ws_L1(a) + a.c.off1[b] + (uint64_t)q * a.c.cap1[b] + (uint64_t)j * kH2Chunk;
-    const uint32_t g0 = b << (a.p.S1 - kS2);  // first sub-bucket of bucket b
+    const uint64_t nchunks = (a.p.C + kPChunk - 1) / kPChunk;
+    const uint32_t lane = __lane_id(), wv = threadIdx.x / 64;
+    const uint32_t wbase = wv * (kPPer * 64);
+    // second endpoints: wave w reads targets e0 + (24*64) w + 64 q + lane
+    // (64 consecutive 4-byte targets per load, the address a wave-uniform
+    // base plus the lane offset), kept as window-relative sub-bucket (high
+    // bits) and local index; entries outside the window or past the chunk
+    // become ~0.  The next chunk is loaded while the current one is written
+    // out, into the same (by then dead) registers.
+    uint32_t v[kPPer];
+    auto load = [&](uint64_t ch) {  // raw loads only: no wait for the data here
+        const uint64_t e0 = ch * kPChunk;
+        const uint32_t len = (uint32_t)min((uint64_t)kPChunk, a.p.C - e0);
+        const uint32_t *wsrc = ws_V(a) + e0 + wbase;
+#pragma unroll
+        for (uint32_t q = 0; q < kPPer; q++) v[q] = wbase + q * 64 + lane < len ? wsrc[q * 64 + lane] : 0u;
+    };
+    if ((uint64_t)blk < nchunks) load(blk);
+    for (uint64_t ch = blk; ch < nchunks; ch += P) {
+        const uint32_t len = (uint32_t)min((uint64_t)kPChunk, a.p.C - ch * kPChunk);
+        for (uint32_t b = threadIdx.x; b < kWin; b += kPBlock) cnt[b] = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < kPPer; q++) {
+            const uint32_t r = (v[q] >> kS2) - g0;
+            v[q] = (wbase + q * 64 + lane < len && r < nwin) ? (r << kS2) | (v[q] & (kSub - 1)) : 0xFFFFFFFFu;
+        }
+        lds_barrier();
+#pragma unroll
+        for (uint32_t q = 0; q < kPPer; q++)
+            if (v[q] != 0xFFFFFFFFu) atomicAdd(&cnt[v[q] >> kS2], 1u);
+        lds_barrier();
+        // exclusive scan over the window (two bins per thread), destinations
+        const uint32_t c0 = cnt[2 * threadIdx.x], c1 = cnt[2 * threadIdx.x + 1];
+        uint32_t total;
+        const uint32_t s0 = block_exclusive_scan<uint32_t>(c0 + c1, scan_sh, &total);
+#pragma unroll
+        for (uint32_t h = 0; h < 2; h++) {
+            const uint32_t b = 2 * threadIdx.x + h;
+            const uint32_t c = h ? c1 : c0, st = h ? s0 + c0 : s0;
+            if (b < nwin && c) {
+                const uint32_t g = g0 + b, f = fill[b], cp = rcap[g];
+                const uint32_t room = f < cp ? cp - f : 0u;
+                // region slot of sorted entry x is dst + x, valid while x < lim
+                dst[b] = off[g] + (uint64_t)blk * cp + f - st;
+                lim[b] = st + min(room, c);
+                fill[b] = f + c;
+            }
+            cnt[b] = st;  // becomes the cursor
+        }
+        lds_barrier();
+#pragma unroll
+        for (uint32_t q = 0; q < kPPer; q++)
+            if (v[q] != 0xFFFFFFFFu) stage[atomicAdd(&cnt[v[q] >> kS2], 1u)] = v[q];
+        lds_barrier();
+        if (ch + P < nchunks) load(ch + P);
+        // sorted runs out: consecutive threads take consecutive sorted
+        // entries, so a store covers a few runs of contiguous region slots
+        for (uint32_t x = threadIdx.x; x < total; x += kPBlock) {
+            const uint32_t w = stage[x];
+            const uint32_t b = w >> kS2;
+            if (x < lim[b])
+                L[dst[b] + x] = (uint16_t)(w & (kSub - 1));
+            else
+                deg_atomic_add(a.deg, ((uint64_t)(g0 + b) << kS2) | (w & (kSub - 1)), 1u);
+        }
+        lds_barrier();
+    }
+    uint32_t *gfill = ws_fill(a) + (uint64_t)blk * a.p.NBsub + g0;
+    for (uint32_t b = threadIdx.x; b < nwin; b += kPBlock) gfill[b] = fill[b];
+}
 
-    for (uint32_t s = threadIdx.x; s < NB2; s += kH2Block) cnt[s] = 0;
+// T: per sub-bucket total over its regions (capped fills) and part count.
+__global__ __launch_bounds__(256) void k_deg_tot(DegArgs a)
+{
+    __shared__ uint32_t sh[4];
+    const uint32_t g = blockIdx.x;
+    const uint32_t cp = ws_rcap(a)[g];
+    const uint32_t *fill = ws_fill(a);
+    uint32_t s = 0;
+    for (uint32_t p = threadIdx.x; p < a.p.P; p += 256) s += min(fill[(uint64_t)p * a.p.NBsub + g], cp);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (__lane_id() == 0) sh[threadIdx.x / 64] = s;
     __syncthreads();
-    constexpr uint32_t PER = kH2Chunk / kH2Block;
-    uint32_t e[PER];
-#pragma unroll
-    for (uint32_t t = 0; t < PER; t++) {
-        const uint32_t x = threadIdx.x + t * kH2Block;
-        e[t] = x < len ? src[x] : 0xFFFFFFFFu;
-    }
-#pragma unroll
-    for (uint32_t t = 0; t < PER; t++)
-        if (e[t] != 0xFFFFFFFFu) atomicAdd(&cnt[e[t] >> kS2], 1u);
-    __syncthreads();
-    // exclusive scan of cnt over NB2 bins (each thread a contiguous slice),
-    // and one list reservation per non-empty bin
-    const uint32_t per = (NB2 + kH2Block - 1) / kH2Block;
-    const uint32_t s0 = threadIdx.x * per;
-    uint32_t mine = 0;
-    for (uint32_t s = s0; s < s0 + per && s < NB2; s++) mine += cnt[s];
-    uint32_t total;
-    uint32_t run = block_exclusive_scan<uint32_t>(mine, scan_sh, &total);
-    const uint32_t *cap2 = ws_cap2(a);
-    const uint64_t *off2 = ws_off2(a);
-    for (uint32_t s = s0; s < s0 + per && s < NB2; s++) {
-        const uint32_t c = cnt[s];
-        start[s] = run;
-        cur[s] = run;
-        if (c) {
-            const uint32_t base = atomicAdd(ws_cnt2(a) + g0 + s, c);
-            const uint32_t cp = cap2[g0 + s];
-            const uint32_t room = base < cp ? cp - base : 0u;
-            dst[s] = off2[g0 + s] + base - run;  // list slot of sorted entry x is dst + x
-            lim[s] = run + min(room, c);
-        }
-        run += c;
-    }
-    __syncthreads();
-#pragma unroll
-    for (uint32_t t = 0; t < PER; t++) {
-        if (e[t] != 0xFFFFFFFFu) {
-            const uint32_t slot = atomicAdd(&cur[e[t] >> kS2], 1u);
-            out[slot] = e[t];
-        }
-    }
-    __syncthreads();
-    uint16_t *L2 = ws_L2(a);
-    for (uint32_t x = threadIdx.x; x < len; x += kH2Block) {
-        const uint32_t w = out[x];
-        const uint32_t s = w >> kS2;
-        if (x < lim[s])
-            L2[dst[s] + x] = (uint16_t)(w & (kSub - 1));
-        else
-            __hip_atomic_fetch_add(a.deg + (((uint64_t)b << a.p.S1) | w), 1u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
+        const uint32_t t = sh[0] + sh[1] + sh[2] + sh[3];
+        ws_tot(a)[g] = t;
+        uint32_t np = (t + kHPart - 1) / kHPart;
+        if (np > a.p.P) np = a.p.P;
+        ws_parts(a)[g] = np;
     }
 }
 
-// H2c: count parts per sub-bucket and scan them (one block of 1024).
-__global__ __launch_bounds__(1024) void k_deg_h2c(DegArgs a)
+// S: exclusive scan of the parts over all sub-buckets (one block of 1024).
+__global__ __launch_bounds__(1024) void k_deg_scan(DegArgs a)
 {
     __shared__ uint32_t sh[16];
     const uint32_t N = a.p.NBsub;
-    const uint32_t *cnt2 = ws_cnt2(a), *cap2 = ws_cap2(a);
-    uint32_t *parts = ws_parts(a), *off = ws_partoff(a);
+    const uint32_t *parts = ws_parts(a);
+    uint32_t *off = ws_partoff(a);
     uint32_t carry = 0;
     for (uint32_t i0 = 0; i0 < N; i0 += 1024) {
         const uint32_t i = i0 + threadIdx.x;
-        uint32_t x = 0;
-        if (i < N) {
-            const uint32_t len = min(cnt2[i], cap2[i]);
-            x = (len + kH3Part - 1) / kH3Part;
-            parts[i] = x;
-        }
+        const uint32_t x = i < N ? parts[i] : 0u;
         uint32_t tot;
         const uint32_t ex = block_exclusive_scan<uint32_t>(x, sh, &tot);
         if (i < N) off[i] = carry + ex;
@@ -361,57 +339,63 @@ __global__ __launch_bounds__(1024) void k_deg_h2c(DegArgs a)
     if (threadIdx.x == 0) off[N] = carry;
 }
 
-// H3: one block per part: LDS histogram of the part's entries, added to deg.
-__global__ __launch_bounds__(kH3Block) void k_deg_h3(DegArgs a)
+// H: one block per part (sub-bucket g, the regions of a contiguous range of
+// partition blocks): LDS histogram, then the counts go to deg.
+__global__ __launch_bounds__(kHBlock) void k_deg_hist(DegArgs a)
 {
     __shared__ uint32_t cnt[kSub];
     const uint32_t N = a.p.NBsub;
-    const uint32_t *off = ws_partoff(a);
+    const uint32_t *poff = ws_partoff(a);
     const uint32_t k = blockIdx.x;
-    if (k >= off[N]) return;
-    uint32_t lo = 0, hi = N;  // sub-bucket g with off[g] <= k < off[g+1]
+    if (k >= poff[N]) return;
+    uint32_t lo = 0, hi = N;  // sub-bucket g with poff[g] <= k < poff[g+1]
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) / 2;
-        if (off[mid] <= k) lo = mid; else hi = mid;
+        if (poff[mid] <= k) lo = mid; else hi = mid;
     }
     const uint32_t g = lo;
-    const uint32_t p = k - off[g];
-    const uint32_t nparts = ws_parts(a)[g];
-    const uint32_t len = min(ws_cnt2(a)[g], ws_cap2(a)[g]);
-    const uint32_t e0 = p * kH3Part, e1 = min(len, e0 + kH3Part);
-    const uint16_t *src = ws_L2(a) + ws_off2(a)[g];
+    const uint32_t np = ws_parts(a)[g], j = k - poff[g];
+    const uint32_t P = a.p.P;
+    const uint32_t p0 = (uint32_t)((uint64_t)P * j / np), p1 = (uint32_t)((uint64_t)P * (j + 1) / np);
+    const uint32_t cp = ws_rcap(a)[g];
+    const uint64_t base = ws_off(a)[g];
+    const uint32_t *fill = ws_fill(a);
+    const uint16_t *L = ws_L(a);
 
-    for (uint32_t x = threadIdx.x; x < kSub; x += kH3Block) cnt[x] = 0;
+    for (uint32_t x = threadIdx.x; x < kSub; x += kHBlock) cnt[x] = 0;
     __syncthreads();
-    // 16-bit entries: the unaligned head singly, then 8 per 16-byte load
-    const uint64_t soff = ws_off2(a)[g];
-    const uint32_t head = min(e1 - e0, (uint32_t)((8 - ((soff + e0) & 7)) & 7));
-    if (threadIdx.x < head) atomicAdd(&cnt[src[e0 + threadIdx.x]], 1u);
-    const uint32_t v0 = e0 + head;
-    const uint32_t nvec = (e1 - v0) / 8;
-    const uint4 *vsrc = reinterpret_cast<const uint4 *>(src + v0);
-    for (uint32_t t = threadIdx.x; t < nvec; t += kH3Block) {
-        const uint4 q = vsrc[t];
-        atomicAdd(&cnt[q.x & 0xFFFFu], 1u);
-        atomicAdd(&cnt[q.x >> 16], 1u);
-        atomicAdd(&cnt[q.y & 0xFFFFu], 1u);
-        atomicAdd(&cnt[q.y >> 16], 1u);
-        atomicAdd(&cnt[q.z & 0xFFFFu], 1u);
-        atomicAdd(&cnt[q.z >> 16], 1u);
-        atomicAdd(&cnt[q.w & 0xFFFFu], 1u);
-        atomicAdd(&cnt[q.w >> 16], 1u);
+    // each wave takes whole regions; 8 entries per 16-byte load where aligned
+    const uint32_t lane = __lane_id(), wv = threadIdx.x / 64;
+    for (uint32_t p = p0 + wv; p < p1; p += kHBlock / 64) {
+        const uint32_t n = min(fill[(uint64_t)p * N + g], cp);
+        const uint16_t *src = L + base + (uint64_t)p * cp;
+        const uint32_t head = min(n, (uint32_t)((8 - (((uintptr_t)src >> 1) & 7)) & 7));
+        if (lane < head) atomicAdd(&cnt[src[lane]], 1u);
+        const uint32_t nv = (n - head) / 8;
+        const uint4 *vs = reinterpret_cast<const uint4 *>(src + head);
+        for (uint32_t t = lane; t < nv; t += 64) {
+            const uint4 q = vs[t];
+            atomicAdd(&cnt[q.x & 0xFFFFu], 1u);
+            atomicAdd(&cnt[q.x >> 16], 1u);
+            atomicAdd(&cnt[q.y & 0xFFFFu], 1u);
+            atomicAdd(&cnt[q.y >> 16], 1u);
+            atomicAdd(&cnt[q.z & 0xFFFFu], 1u);
+            atomicAdd(&cnt[q.z >> 16], 1u);
+            atomicAdd(&cnt[q.w & 0xFFFFu], 1u);
+            atomicAdd(&cnt[q.w >> 16], 1u);
+        }
+        for (uint32_t x = head + nv * 8 + lane; x < n; x += 64) atomicAdd(&cnt[src[x]], 1u);
     }
-    for (uint32_t x = v0 + nvec * 8 + threadIdx.x; x < e1; x += kH3Block) atomicAdd(&cnt[src[x]], 1u);
     __syncthreads();
     const uint64_t vbase = (uint64_t)g << kS2;
-    for (uint32_t y = threadIdx.x; y < kSub; y += kH3Block) {
+    for (uint32_t y = threadIdx.x; y < kSub; y += kHBlock) {
         const uint64_t v = vbase + y;
         const uint32_t c = cnt[y];
-        if (c && v < a.n) {
-            if (nparts == 1)
+        if (c && v < a.p.n) {
+            if (np == 1)
                 a.deg[v] += c;
             else
-                __hip_atomic_fetch_add(a.deg + v, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                deg_atomic_add(a.deg, v, c);
         }
     }
 }
