@@ -106,6 +106,50 @@ __device__ __forceinline__ void store_pair(uint32_t *out, uint32_t j, uint32_t t
     }
 }
 
+// The chain loop of one tile of tn edges (paper Section 2, figure
+// generateEdge): lane-refill over the tile.  rbase = 2*(first edge)+1, so
+// edge li of the tile starts at position rbase + 2*li.  A lane whose chain
+// reaches an even position stores out(r) at stage[li] and takes the next
+// unclaimed edge.  While a whole wave's worth of edges is unclaimed every
+// lane is busy and no per-lane bounds test is needed; the tail then runs
+// the last chains with finished lanes idle.
+template <class R, class H, class O>
+__device__ __forceinline__ void chain_tile(uint32_t *stage, uint32_t tn, uint32_t lane, R rbase, H hash, O out)
+{
+    tn = __builtin_amdgcn_readfirstlane(tn);  // wave-uniform: keeps loop control scalar
+    uint32_t li = lane;
+    uint32_t next = kWave;  // next unclaimed edge (wave-uniform)
+    R r = rbase + 2 * (R)li;
+    if (tn >= kWave) {
+        while (next + kWave <= tn) {
+            r = hash(r);
+            const uint64_t dm = __ballot(!(r & 1));
+            if (!(r & 1)) {
+                stage[li] = out(r);
+                li = next + lane_rank(dm);
+                r = rbase + 2 * (R)li;
+            }
+            next += (uint32_t)__popcll(dm);
+        }
+    }
+    // tail: at most 64 chains in flight, no more than tn - next left to claim
+    bool active = li < tn;
+    uint64_t live = __ballot(active);
+    while (live) {
+        r = hash(r);
+        const bool done = active && !(r & 1);
+        const uint64_t dm = __ballot(done);
+        if (done) {
+            stage[li] = out(r);
+            li = next + lane_rank(dm);
+            active = li < tn;
+            r = rbase + 2 * (R)li;
+        }
+        next += (uint32_t)__popcll(dm);
+        live = __ballot(active);
+    }
+}
+
 // One chain step for every lane, then refill of the lanes that finished.
 // NARROW: all positions of the launch are below 2^32.
 template <bool NARROW, bool VEC16, bool VLIST>
@@ -122,43 +166,12 @@ __global__ __launch_bounds__(kGenBlock) void k_gen_u32(GenArgs a)
         const uint32_t tn = (uint32_t)min((uint64_t)kTile, a.count - off);
         const uint64_t ibase = a.begin + off;
 
-        uint32_t li = lane;
-        bool active = li < tn;
-        uint32_t next = kWave;
-        uint32_t remaining = tn;
-        if constexpr (NARROW) {
-            uint32_t r = 2u * ((uint32_t)ibase + li) + 1u;
-            while (remaining) {
-                r = hash_narrow(r, a.key);
-                const bool done = active && !(r & 1u);
-                const uint64_t dm = __ballot(done);
-                if (done) {
-                    stage[li] = r >> 1;
-                    li = next + lane_rank(dm);
-                    active = li < tn;
-                    r = 2u * ((uint32_t)ibase + li) + 1u;
-                }
-                const uint32_t nd = (uint32_t)__popcll(dm);
-                next += nd;
-                remaining -= nd;
-            }
-        } else {
-            uint64_t r = 2 * (ibase + li) + 1;
-            while (remaining) {
-                r = hash_wide(r, a.key);
-                const bool done = active && !(r & 1u);
-                const uint64_t dm = __ballot(done);
-                if (done) {
-                    stage[li] = (uint32_t)div64(r >> 1, a.div);
-                    li = next + lane_rank(dm);
-                    active = li < tn;
-                    r = 2 * (ibase + li) + 1;
-                }
-                const uint32_t nd = (uint32_t)__popcll(dm);
-                next += nd;
-                remaining -= nd;
-            }
-        }
+        if constexpr (NARROW)
+            chain_tile(stage, tn, lane, (uint32_t)(2 * ibase + 1), [&](uint32_t r) { return hash_narrow(r, a.key); },
+                       [](uint32_t r) { return r >> 1; });
+        else
+            chain_tile(stage, tn, lane, 2 * ibase + 1, [&](uint64_t r) { return hash_wide(r, a.key); },
+                       [&](uint64_t r) { return (uint32_t)div64(r >> 1, a.div); });
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
