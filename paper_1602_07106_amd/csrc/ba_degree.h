@@ -214,50 +214,76 @@ __global__ __launch_bounds__(1024) void k_deg_plan(DegArgs a)
 
 // P: partition of second endpoints into per-(block, sub-bucket) regions,
 // for sub-buckets g0 .. g0+kWin-1.
+//
+// Region slots are addressed relative to the window's first region in 32
+// bits: a window spans at most sum(cap) * P <= 1.15 C + 8 sqrt(P kWin C) +
+// 64 P kWin slots (Cauchy-Schwarz over its sub-buckets, capacity scale <= 1),
+// under 3.2e9 for C <= kPieceMax, P <= kPBlocksMax.
 __global__ __launch_bounds__(kPBlock) void k_deg_part(DegArgs a)
 {
-    __shared__ uint32_t cnt[kWin], lim[kWin], fill[kWin];
-    __shared__ uint64_t dst[kWin];
-    __shared__ uint32_t stage[kPChunk];  // sorted (bin << 15 | local index)
+    constexpr uint32_t kOut = kWin << kS2;  // entry outside the window or past the chunk
+    __shared__ uint32_t cnt[kWin];         // per chunk: counts, then cursors
+    __shared__ uint32_t fill[kWin];        // entries this block has sent to each region
+    __shared__ uint32_t cap[kWin];         // region capacity
+    __shared__ uint32_t rbase[kWin];       // this block's region start, window-relative
+    __shared__ uint2 dl[kWin];             // per chunk: (slot of sorted entry 0, slot limit)
+    __shared__ uint32_t stage[kPChunk];    // sorted (bin << 15 | local index)
     __shared__ uint32_t scan_sh[16];
     const uint32_t g0 = a.g0;
     const uint32_t nwin = min(kWin, a.p.NBsub - g0);
     const uint32_t blk = blockIdx.x, P = gridDim.x;
-    const uint32_t *rcap = ws_rcap(a);
-    const uint64_t *off = ws_off(a);
-    uint16_t *L = ws_L(a);
-    for (uint32_t b = threadIdx.x; b < kWin; b += kPBlock) fill[b] = 0;
+    const uint64_t wslot = ws_off(a)[g0];
+    uint16_t *Lw = ws_L(a) + wslot;
+    for (uint32_t b = threadIdx.x; b < kWin; b += kPBlock) {
+        const uint32_t cp = b < nwin ? ws_rcap(a)[g0 + b] : 0u;
+        fill[b] = 0;
+        cap[b] = cp;
+        rbase[b] = b < nwin ? (uint32_t)(ws_off(a)[g0 + b] - wslot + (uint64_t)blk * cp) : 0u;
+    }
 
     const uint64_t nchunks = (a.p.C + kPChunk - 1) / kPChunk;
     const uint32_t lane = __lane_id(), wv = threadIdx.x / 64;
     const uint32_t wbase = wv * (kPPer * 64);
     // second endpoints: wave w reads targets e0 + (24*64) w + 64 q + lane
-    // (64 consecutive 4-byte targets per load, the address a wave-uniform
-    // base plus the lane offset), kept as window-relative sub-bucket (high
-    // bits) and local index; entries outside the window or past the chunk
-    // become ~0.  The next chunk is loaded while the current one is written
-    // out, into the same (by then dead) registers.
+    // (64 consecutive 4-byte targets per load).  The next chunk is loaded
+    // while the current one is written out, into the same (by then dead)
+    // registers; whole chunks load unconditionally so that the loads are
+    // issued back to back, only the last, partial chunk tests each index.
     uint32_t v[kPPer];
-    auto load = [&](uint64_t ch) {  // raw loads only: no wait for the data here
+    auto load = [&](uint64_t ch) {
         const uint64_t e0 = ch * kPChunk;
-        const uint32_t len = (uint32_t)min((uint64_t)kPChunk, a.p.C - e0);
-        const uint32_t *wsrc = ws_V(a) + e0 + wbase;
+        const uint32_t *wsrc = ws_V(a) + e0 + wbase + lane;
+        if (e0 + kPChunk <= a.p.C) {
 #pragma unroll
-        for (uint32_t q = 0; q < kPPer; q++) v[q] = wbase + q * 64 + lane < len ? wsrc[q * 64 + lane] : 0u;
+            for (uint32_t q = 0; q < kPPer; q++) v[q] = wsrc[q * 64];
+        } else {
+            const uint32_t len = (uint32_t)(a.p.C - e0);
+#pragma unroll
+            for (uint32_t q = 0; q < kPPer; q++) v[q] = wbase + q * 64 + lane < len ? wsrc[q * 64] : 0u;
+        }
     };
     if ((uint64_t)blk < nchunks) load(blk);
     for (uint64_t ch = blk; ch < nchunks; ch += P) {
-        const uint32_t len = (uint32_t)min((uint64_t)kPChunk, a.p.C - ch * kPChunk);
+        const uint64_t e0 = ch * kPChunk;
         for (uint32_t b = threadIdx.x; b < kWin; b += kPBlock) cnt[b] = 0;
+        if (e0 + kPChunk <= a.p.C) {
 #pragma unroll
-        for (uint32_t q = 0; q < kPPer; q++) {
-            const uint32_t r = (v[q] >> kS2) - g0;
-            v[q] = (wbase + q * 64 + lane < len && r < nwin) ? (r << kS2) | (v[q] & (kSub - 1)) : 0xFFFFFFFFu;
+            for (uint32_t q = 0; q < kPPer; q++) {
+                const uint32_t r = (v[q] >> kS2) - g0;
+                v[q] = r < nwin ? (r << kS2) | (v[q] & (kSub - 1)) : kOut;
+            }
+        } else {
+            const uint32_t len = (uint32_t)(a.p.C - e0);
+#pragma unroll
+            for (uint32_t q = 0; q < kPPer; q++) {
+                const uint32_t r = (v[q] >> kS2) - g0;
+                v[q] = (wbase + q * 64 + lane < len && r < nwin) ? (r << kS2) | (v[q] & (kSub - 1)) : kOut;
+            }
         }
         lds_barrier();
 #pragma unroll
         for (uint32_t q = 0; q < kPPer; q++)
-            if (v[q] != 0xFFFFFFFFu) atomicAdd(&cnt[v[q] >> kS2], 1u);
+            if (v[q] != kOut) atomicAdd(&cnt[v[q] >> kS2], 1u);
         lds_barrier();
         // exclusive scan over the window (two bins per thread), destinations
         const uint32_t c0 = cnt[2 * threadIdx.x], c1 = cnt[2 * threadIdx.x + 1];
@@ -267,31 +293,48 @@ __global__ __launch_bounds__(kPBlock) void k_deg_part(DegArgs a)
         for (uint32_t h = 0; h < 2; h++) {
             const uint32_t b = 2 * threadIdx.x + h;
             const uint32_t c = h ? c1 : c0, st = h ? s0 + c0 : s0;
-            if (b < nwin && c) {
-                const uint32_t g = g0 + b, f = fill[b], cp = rcap[g];
+            if (c) {
+                const uint32_t f = fill[b], cp = cap[b];
                 const uint32_t room = f < cp ? cp - f : 0u;
-                // region slot of sorted entry x is dst + x, valid while x < lim
-                dst[b] = off[g] + (uint64_t)blk * cp + f - st;
-                lim[b] = st + min(room, c);
+                // region slot of sorted entry x is dst + x (mod 2^32), valid while x < lim
+                dl[b] = make_uint2(rbase[b] + f - st, st + min(room, c));
                 fill[b] = f + c;
             }
             cnt[b] = st;  // becomes the cursor
         }
         lds_barrier();
+        // scatter into sorted order: eight cursor bumps in flight at a time
 #pragma unroll
-        for (uint32_t q = 0; q < kPPer; q++)
-            if (v[q] != 0xFFFFFFFFu) stage[atomicAdd(&cnt[v[q] >> kS2], 1u)] = v[q];
+        for (uint32_t q0 = 0; q0 < kPPer; q0 += 8) {
+            uint32_t pos[8];
+#pragma unroll
+            for (uint32_t j = 0; j < 8; j++)
+                pos[j] = v[q0 + j] != kOut ? atomicAdd(&cnt[v[q0 + j] >> kS2], 1u) : ~0u;
+#pragma unroll
+            for (uint32_t j = 0; j < 8; j++)
+                if (pos[j] != ~0u) stage[pos[j]] = v[q0 + j];
+        }
         lds_barrier();
         if (ch + P < nchunks) load(ch + P);
         // sorted runs out: consecutive threads take consecutive sorted
         // entries, so a store covers a few runs of contiguous region slots
-        for (uint32_t x = threadIdx.x; x < total; x += kPBlock) {
-            const uint32_t w = stage[x];
-            const uint32_t b = w >> kS2;
-            if (x < lim[b])
-                L[dst[b] + x] = (uint16_t)(w & (kSub - 1));
-            else
-                deg_atomic_add(a.deg, ((uint64_t)(g0 + b) << kS2) | (w & (kSub - 1)), 1u);
+        for (uint32_t x0 = threadIdx.x; x0 < total; x0 += 4 * kPBlock) {
+            uint32_t w[4];
+            uint2 t[4];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; u++) w[u] = x0 + u * kPBlock < total ? stage[x0 + u * kPBlock] : 0u;
+#pragma unroll
+            for (uint32_t u = 0; u < 4; u++) t[u] = dl[w[u] >> kS2];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; u++) {
+                const uint32_t x = x0 + u * kPBlock;
+                if (x < total) {
+                    if (x < t[u].y)
+                        Lw[t[u].x + x] = (uint16_t)(w[u] & (kSub - 1));
+                    else
+                        deg_atomic_add(a.deg, ((uint64_t)(g0 + (w[u] >> kS2)) << kS2) | (w[u] & (kSub - 1)), 1u);
+                }
+            }
         }
         lds_barrier();
     }
