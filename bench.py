@@ -2,17 +2,18 @@
 
 One step = the whole hot path on the 2^26-node, d=16, seed=7 graph
 (1,073,741,824 edges): every edge computed by its own hash chain, the full
-uint32 edge array (8 GiB) written to HBM and the fused uint32 degree array of
+uint32 edge array (8 GiB) written to HBM and the full uint32 degree array of
 all 2^26 nodes.  Outputs and the degree workspace stay allocated across steps
 (the inputs are three integers), so a timed step is pure GPU work.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
 Prints one JSON line.  `value` is edges per second of the timed steps.
-`roofline` is that of the dominant kernel (the per-edge chain kernel with
-its fused coarse partition of second endpoints), timed live with HIP events
-on its own stream; `cpu_baseline` times the CPU oracle (sequential
-Batagelj-Brandes plus the degree count) on a bounded prefix of the same graph.
+Every kernel of a step is timed live with HIP events on the stream it runs
+on (the library's timing hook); `roofline` is that of the kernel with the
+largest share of the step, `kernels` gives every kernel's share and roofline
+fraction.  `cpu_baseline` times the CPU oracle (sequential Batagelj-Brandes
+plus the degree count) on a bounded prefix of the same graph.
 """
 from __future__ import annotations
 
@@ -30,17 +31,27 @@ if ROOT not in sys.path:
 
 N, D, SEED = 1 << 26, 16, 7
 M = N * D
-HBM_PEAK_GBPS = 8000.0                    # MI355X HBM3E
-VALU_PEAK = 256 * 64 * 2.4e9              # 32-bit lane-ops/s, one per lane per clock
-# Algorithmic work of the chain kernel per edge (derivation in the design doc):
-# hash evaluations per edge for this graph (2,147,478,402 over its 2^30
-# edges, counted by the CPU oracle), VALU issue cycles per evaluation of the
-# narrow (r < 2^32) hash, and fixed cycles per edge.
+HBM_PEAK = 8.0e12                          # MI355X HBM3E, bytes/s
+VALU_PEAK = 256 * 64 * 2.4e9               # 32-bit lane-cycles/s: 256 CUs x 64 lanes x 2.4 GHz
+# Algorithmic work per edge (derivations in the design doc):
+#  chain kernel: hash evaluations per edge of this graph (2,147,478,402 over
+#  its 2^30 edges, counted by the CPU oracle) x VALU issue cycles of one
+#  narrow (r < 2^32) evaluation, plus fixed cycles per edge; it writes the
+#  8-byte edge pair and the 4-byte target of the degree pipeline;
+#  partition: reads the 4-byte target, writes a 2-byte local index;
+#  histogram: reads the 2-byte index; adds into the 4-byte count of each node.
 HASH_PER_EDGE = 2147478402 / M
 CYCLES_PER_HASH = 17.0
 CYCLES_PER_EDGE = 2.0
-BYTES_PER_EDGE = 8.0                      # the uint32 (u, v) pair written per edge
-PROFILE = os.path.join(ROOT, "profiles", "gen_partition_n2e26_d16_traffic.md")
+GEN_BYTES_PER_EDGE = 12.0
+PART_BYTES_PER_EDGE = 6.0
+HIST_BYTES = 2.0 * M + 8.0 * N
+KERNEL_NAMES = {
+    "gen": "k_gen_u32 (chain + edge pairs + target list)",
+    "part": "k_deg_part (radix partition of targets)",
+    "hist": "k_deg_hist (LDS histograms into deg)",
+}
+PROFILE = os.path.join(ROOT, "profiles", "pipeline_n2e26_d16_hbm_traffic.md")
 KERNEL_SOURCES = [
     os.path.join(ROOT, "paper_1602_07106_amd", "csrc", f) for f in ("ba.hip", "ba_device.h", "ba_degree.h")
 ]
@@ -54,18 +65,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_traffic():
-    """HBM bytes per launch of the chain kernel from the committed rocprofv3
-    counter summary, or None when absent or taken on different kernel source."""
+def committed_traffic() -> dict:
+    """HBM bytes per launch of each kernel kind from the committed rocprofv3
+    counter summary; empty when absent or taken on different kernel source."""
     try:
         txt = open(PROFILE).read()
     except OSError:
-        return None
+        return {}
     m_src = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", txt)
-    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m_src or not m_b or m_src.group(1) != kernel_source_hash():
-        return None
-    return float(m_b.group(1))
+    if not m_src or m_src.group(1) != kernel_source_hash():
+        return {}
+    return {k: float(v) for k, v in re.findall(r"hbm_bytes_per_launch\[(\w+)\]:\s*([0-9.eE+]+)", txt)}
 
 
 def cpu_baseline():
@@ -101,6 +111,26 @@ def copy_calibration(nbytes: int) -> int:
     return 0
 
 
+def kernel_rooflines(per_launch_s: dict) -> dict:
+    """Roofline of each main kernel from its measured mean launch time."""
+    out = {}
+    t = per_launch_s.get("gen")
+    if t:
+        cyc = (HASH_PER_EDGE * CYCLES_PER_HASH + CYCLES_PER_EDGE) * M
+        alu = cyc / t
+        hbm = GEN_BYTES_PER_EDGE * M / t
+        out["gen"] = {"bound": "alu", "achieved": alu / 1e12, "peak": VALU_PEAK / 1e12, "unit": "Tlane-cycles/s",
+                      "frac": alu / VALU_PEAK, "hbm_frac": hbm / HBM_PEAK, "alg_bytes": GEN_BYTES_PER_EDGE * M,
+                      "alg_cycles": cyc}
+    for k, nbytes in (("part", PART_BYTES_PER_EDGE * M), ("hist", HIST_BYTES)):
+        t = per_launch_s.get(k)
+        if t:
+            bw = nbytes / t
+            out[k] = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                      "frac": bw / HBM_PEAK, "alg_bytes": nbytes}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,8 +143,8 @@ def main() -> int:
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the generator here has no multi-GPU path "
+              "(DESIGN.md describes how it would shard); use --gpus 1", file=sys.stderr)
         return 2
 
     import torch
@@ -134,6 +164,7 @@ def main() -> int:
         step()
     torch.cuda.synchronize()
 
+    # the library launches on torch's current stream, where these events sit
     ba.kernel_timing(True)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -146,33 +177,34 @@ def main() -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = e0.elapsed_time(e1)
-    kern_ms, launches = ba.kernel_timing_read()
+    kt = ba.kernel_timing_read()
     ba.kernel_timing(False)
-    kern_avg = kern_ms / max(1, launches)
 
     ms_per_step = gpu_ms / args.steps
     value = M * args.steps / (gpu_ms / 1e3)
 
-    # roofline of the chain kernel: both bounds, the binding one reported
-    t_hbm = BYTES_PER_EDGE * M / (HBM_PEAK_GBPS * 1e9)
-    t_alu = (HASH_PER_EDGE * CYCLES_PER_HASH + CYCLES_PER_EDGE) * M / VALU_PEAK
-    kern_s = kern_avg / 1e3
-    hbm_achieved = BYTES_PER_EDGE * M / kern_s / 1e9
-    alu_achieved = (HASH_PER_EDGE * CYCLES_PER_HASH + CYCLES_PER_EDGE) * M / kern_s / 1e12
+    per_launch_s = {k: ms / n / 1e3 for k, (ms, n) in kt.items() if n}
+    roofs = kernel_rooflines(per_launch_s)
     traffic = committed_traffic()
-    if t_hbm >= t_alu:
-        roof = {"bound": "hbm", "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(hbm_achieved / HBM_PEAK_GBPS, 4), "traffic": traffic}
-    else:
-        roof = {"bound": "alu", "achieved": round(alu_achieved, 2), "peak": round(VALU_PEAK / 1e12, 2),
-                "unit": "Tlane-cycles/s", "frac": round(alu_achieved * 1e12 / VALU_PEAK, 4), "traffic": traffic}
-    roof.update({
-        "kernel": "k_gen_u32 (chain + coarse partition)",
-        "kernel_ms": round(kern_avg, 4),
-        "launches": launches,
-        "alu_frac": round(alu_achieved * 1e12 / VALU_PEAK, 4),
-        "hbm_frac": round(hbm_achieved / HBM_PEAK_GBPS, 4),
-    })
+    kernels = {}
+    for k, (ms, n) in kt.items():
+        if not n:
+            continue
+        e = {"ms_per_launch": round(ms / n, 4), "launches": n, "share_of_step": round(ms / gpu_ms, 4)}
+        if k in roofs:
+            e.update({"bound": roofs[k]["bound"], "frac": round(roofs[k]["frac"], 4)})
+            if "hbm_frac" in roofs[k]:
+                e["hbm_frac"] = round(roofs[k]["hbm_frac"], 4)
+        kernels[k] = e
+    dom = max(roofs, key=lambda k: kt[k][0])
+    r = roofs[dom]
+    roof = {"bound": r["bound"], "achieved": round(r["achieved"], 2), "peak": round(r["peak"], 2), "unit": r["unit"],
+            "frac": round(r["frac"], 4), "traffic": traffic.get(dom),
+            "kernel": KERNEL_NAMES[dom], "kernel_ms": round(per_launch_s[dom] * 1e3, 4), "launches": kt[dom][1],
+            "alg_bytes_per_launch": r["alg_bytes"]}
+    if "alg_cycles" in r:
+        roof["alg_lane_cycles_per_launch"] = r["alg_cycles"]
+        roof["hbm_frac"] = round(r["hbm_frac"], 4)
 
     line = {
         "metric": "edges/s at n=2^26,d=16 (bit-exact)",
@@ -187,9 +219,10 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic (the generator is the workload: n, d, seed)",
-        "config": {"workload": "plain BA, empty seed graph: n=2^26, d=16, seed=7, uint32 edge pairs + fused "
+        "config": {"workload": "plain BA, empty seed graph: n=2^26, d=16, seed=7, uint32 edge pairs + full "
                                "uint32 degree array", "edges": M, "n": N, "d": D, "seed": SEED},
         "roofline": roof,
+        "kernels": kernels,
         "wall_s": round(wall, 3),
     }
     if not args.no_cpu_baseline:

@@ -141,14 +141,24 @@ int ba_degrees_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin,
 /*
  * Measurement hook for benchmarks (not needed to generate graphs).
  * ba_kernel_timing(1) makes every later call on this host thread record a
- * HIP event pair on its stream around its generator kernel (the per-edge
- * chain kernel, which dominates a call); ba_kernel_timing(0) stops and drops
- * what was recorded.  ba_kernel_timing_read waits for the recorded events and
- * returns the summed kernel time (ms) and the number of launches since the
- * last enable/read, then starts a new accumulation.
+ * HIP event pair on its stream around each kernel it launches, tagged with
+ * the kind of kernel; ba_kernel_timing(0) stops and drops what was recorded.
+ * ba_kernel_timing_read waits for the recorded events and fills ms[k] (summed
+ * kernel milliseconds) and launches[k] for every kind k < BA_KT_COUNT since
+ * the last enable/read, then starts a new accumulation.  Both arrays are
+ * caller-owned host memory of BA_KT_COUNT elements.  Events add a little
+ * host overhead per launch, so leave timing off outside measurements.
  */
+enum {
+    BA_KT_GEN = 0,     /* per-edge chain kernels (edge array, target list) */
+    BA_KT_PART = 1,    /* degree pipeline: radix partition of targets */
+    BA_KT_HIST = 2,    /* degree pipeline: LDS histograms into deg */
+    BA_KT_STREAM = 3,  /* streaming first-k degrees and checksum */
+    BA_KT_OTHER = 4,   /* fills, plan, totals, scans, tail */
+    BA_KT_COUNT = 5
+};
 int ba_kernel_timing(int enable);
-int ba_kernel_timing_read(double *ms_total, uint64_t *launches);
+int ba_kernel_timing_read(double *ms, uint64_t *launches);
 
 /* Text for a status code (static storage, never NULL). */
 const char *ba_strerror(int status);

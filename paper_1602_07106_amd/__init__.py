@@ -20,7 +20,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from typing import Optional, Tuple
+from typing import Dict, Optional, Tuple
 
 import torch
 
@@ -28,6 +28,7 @@ from . import build as _build
 
 __all__ = [
     "BAError",
+    "KERNEL_KINDS",
     "workspace",
     "workspace_bytes",
     "generate",
@@ -42,6 +43,8 @@ __all__ = [
 ]
 
 BA_OK, BA_EINVAL, BA_ERANGE, BA_EDEVICE = 0, -1, -2, -4
+# kernel kinds of the timing hook (BA_KT_* in include/ba.h)
+KERNEL_KINDS = ("gen", "part", "hist", "stream", "other")
 
 
 class BAError(RuntimeError):
@@ -212,16 +215,18 @@ def generate_range(
 
 
 def kernel_timing(enable: bool) -> None:
-    """Start (or stop) recording HIP events around the generator kernel of
-    every call made by this thread (see ba_kernel_timing)."""
+    """Start (or stop) recording HIP events around every kernel launched by
+    this thread's calls (see ba_kernel_timing)."""
     _check("ba_kernel_timing", lib().ba_kernel_timing(1 if enable else 0))
 
 
-def kernel_timing_read() -> Tuple[float, int]:
-    """(summed generator-kernel milliseconds, launches) since the last read."""
-    ms, n = ctypes.c_double(0.0), ctypes.c_uint64(0)
+def kernel_timing_read() -> Dict[str, Tuple[float, int]]:
+    """{kind: (summed kernel milliseconds, launches)} since the last read,
+    for every kind in KERNEL_KINDS."""
+    k = len(KERNEL_KINDS)
+    ms, n = (ctypes.c_double * k)(), (ctypes.c_uint64 * k)()
     _check("ba_kernel_timing_read", lib().ba_kernel_timing_read(ctypes.addressof(ms), ctypes.addressof(n)))
-    return ms.value, n.value
+    return {name: (ms[i], n[i]) for i, name in enumerate(KERNEL_KINDS)}
 
 
 def generate_range_u64(n: int, d: int, seed: int, begin: int, count: int, *, device=None) -> torch.Tensor:

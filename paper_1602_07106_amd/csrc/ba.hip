@@ -388,13 +388,47 @@ static uint32_t grid_for(uint64_t units, uint64_t per_block, uint64_t cap)
     return (uint32_t)b;
 }
 
-// Opt-in measurement of the generator kernel (per host thread): an event
-// pair recorded on the launch stream around every generator launch.
+// Opt-in measurement of kernel durations (per host thread): an event pair
+// recorded on the launch stream around every launch, tagged with the kind of
+// kernel (BA_KT_*).
 struct KernelTiming {
+    struct Rec {
+        int kind;
+        hipEvent_t e0, e1;
+    };
     bool on = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<Rec> ev;
 };
 static thread_local KernelTiming g_timing;
+
+// Runs `launch` (which enqueues one kernel on st), bracketed by events when
+// timing is on; returns the launch status.
+template <class F>
+static int launch_timed(int kind, hipStream_t st, F &&launch)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc;
+    if (g_timing.on) {
+        if ((rc = hip_check(hipEventCreate(&e0)))) return rc;
+        if ((rc = hip_check(hipEventCreate(&e1)))) {
+            (void)hipEventDestroy(e0);
+            return rc;
+        }
+        if ((rc = hip_check(hipEventRecord(e0, st)))) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return rc;
+        }
+    }
+    launch();
+    rc = hip_check(hipGetLastError());
+    if (g_timing.on) {
+        const int rc2 = hip_check(hipEventRecord(e1, st));
+        g_timing.ev.push_back({kind, e0, e1});
+        if (!rc) rc = rc2;
+    }
+    return rc;
+}
 
 template <bool N, bool V, bool L>
 static int launch_gen_one(const GenArgs &a, hipStream_t st)
@@ -403,20 +437,8 @@ static int launch_gen_one(const GenArgs &a, hipStream_t st)
     int rc = persistent_grid(k_gen_u32<N, V, L>, kGenBlock, &grid);
     if (rc) return rc;
     grid = grid_for(a.ntiles, kGenWaves, grid);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (g_timing.on) {
-        if ((rc = hip_check(hipEventCreate(&e0)))) return rc;
-        if ((rc = hip_check(hipEventCreate(&e1)))) return rc;
-        if ((rc = hip_check(hipEventRecord(e0, st)))) return rc;
-    }
-    hipLaunchKernelGGL((k_gen_u32<N, V, L>), dim3(grid), dim3(kGenBlock), 0, st, a);
-    rc = hip_check(hipGetLastError());
-    if (g_timing.on) {
-        const int rc2 = hip_check(hipEventRecord(e1, st));
-        g_timing.ev.emplace_back(e0, e1);
-        if (!rc) rc = rc2;
-    }
-    return rc;
+    return launch_timed(BA_KT_GEN, st,
+                        [&] { hipLaunchKernelGGL((k_gen_u32<N, V, L>), dim3(grid), dim3(kGenBlock), 0, st, a); });
 }
 
 // Generator over edges begin .. begin+count-1 writing edge pairs to `edges`
@@ -490,20 +512,27 @@ static int degrees_of_targets(uint64_t n, uint32_t d, uint64_t begin, uint64_t c
     a.deg = deg;
     a.ws = (unsigned char *)ws;
     a.scale = deg_cap_scale();
-    hipLaunchKernelGGL(k_deg_plan, dim3(1), dim3(1024), 0, st, a);
-    if ((rc = hip_check(hipGetLastError()))) return rc;
+    if ((rc = launch_timed(BA_KT_OTHER, st, [&] { hipLaunchKernelGGL(k_deg_plan, dim3(1), dim3(1024), 0, st, a); })))
+        return rc;
     for (uint32_t w = 0; w < a.p.NW; w++) {
         a.g0 = w * kWin;
-        hipLaunchKernelGGL(k_deg_part, dim3(P), dim3(kPBlock), 0, st, a);
-        if ((rc = hip_check(hipGetLastError()))) return rc;
+        if ((rc = launch_timed(BA_KT_PART, st,
+                               [&] { hipLaunchKernelGGL(k_deg_part, dim3(P), dim3(kPBlock), 0, st, a); })))
+            return rc;
     }
-    hipLaunchKernelGGL(k_deg_tot, dim3(a.p.NBsub), dim3(256), 0, st, a);
-    if ((rc = hip_check(hipGetLastError()))) return rc;
-    hipLaunchKernelGGL(k_deg_scan, dim3(1), dim3(1024), 0, st, a);
-    if ((rc = hip_check(hipGetLastError()))) return rc;
-    const uint64_t parts_max = (uint64_t)a.p.NBsub + (count + kHPart - 1) / kHPart + 1;
-    hipLaunchKernelGGL(k_deg_hist, dim3((uint32_t)parts_max), dim3(kHBlock), 0, st, a);
-    return hip_check(hipGetLastError());
+    if (count % kPChunk) {
+        const uint32_t tb = (uint32_t)((count % kPChunk + 255) / 256);
+        if ((rc = launch_timed(BA_KT_OTHER, st, [&] { hipLaunchKernelGGL(k_deg_tail, dim3(tb), dim3(256), 0, st, a); })))
+            return rc;
+    }
+    if ((rc = launch_timed(BA_KT_OTHER, st,
+                           [&] { hipLaunchKernelGGL(k_deg_tot, dim3(a.p.NBsub), dim3(256), 0, st, a); })))
+        return rc;
+    if ((rc = launch_timed(BA_KT_OTHER, st, [&] { hipLaunchKernelGGL(k_deg_scan, dim3(1), dim3(1024), 0, st, a); })))
+        return rc;
+    const uint32_t parts_max = (uint32_t)((uint64_t)a.p.NBsub + (count + kHPart - 1) / kHPart + 1);
+    return launch_timed(BA_KT_HIST, st,
+                        [&] { hipLaunchKernelGGL(k_deg_hist, dim3(parts_max), dim3(kHBlock), 0, st, a); });
 }
 
 // Edges [begin, begin+count) written to `edges`, their second endpoints
@@ -569,8 +598,8 @@ static int launch_stream_one(StreamArgs a, hipStream_t st)
     a.per_wave = per_wave;
     const uint64_t waves = (a.count + per_wave - 1) / per_wave;
     grid = (uint32_t)((waves + kStreamWaves - 1) / kStreamWaves);
-    hipLaunchKernelGGL((k_stream<N>), dim3(grid), dim3(kStreamBlock), 0, st, a);
-    return hip_check(hipGetLastError());
+    return launch_timed(BA_KT_STREAM, st,
+                        [&] { hipLaunchKernelGGL((k_stream<N>), dim3(grid), dim3(kStreamBlock), 0, st, a); });
 }
 
 static int launch_stream(uint64_t begin, uint64_t count, uint32_t d, uint64_t seed, uint64_t k,
@@ -609,8 +638,9 @@ static int check_generate(uint64_t n, uint32_t d, uint64_t begin, uint64_t count
 static int fill_first_endpoints_whole(uint64_t n, uint32_t d, uint32_t *deg, hipStream_t st)
 {
     if (!deg || !n) return BA_OK;
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256 * 8, 8192)), dim3(256), 0, st, deg, n, d);
-    return hip_check(hipGetLastError());
+    return launch_timed(BA_KT_OTHER, st, [&] {
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256 * 8, 8192)), dim3(256), 0, st, deg, n, d);
+    });
 }
 
 int ba_generate(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint32_t *deg, void *stream)
@@ -755,9 +785,9 @@ int ba_last_hip_error(void) { return g_last_hip; }
 
 static void timing_release()
 {
-    for (auto &p : g_timing.ev) {
-        (void)hipEventDestroy(p.first);
-        (void)hipEventDestroy(p.second);
+    for (auto &r : g_timing.ev) {
+        (void)hipEventDestroy(r.e0);
+        (void)hipEventDestroy(r.e1);
     }
     g_timing.ev.clear();
 }
@@ -769,19 +799,21 @@ int ba_kernel_timing(int enable)
     return BA_OK;
 }
 
-int ba_kernel_timing_read(double *ms_total, uint64_t *launches)
+int ba_kernel_timing_read(double *ms, uint64_t *launches)
 {
-    if (!ms_total || !launches) return BA_EINVAL;
-    double tot = 0.0;
-    int rc = BA_OK;
-    for (auto &p : g_timing.ev) {
-        float ms = 0.0f;
-        if (!rc) rc = hip_check(hipEventSynchronize(p.second));
-        if (!rc) rc = hip_check(hipEventElapsedTime(&ms, p.first, p.second));
-        tot += ms;
+    if (!ms || !launches) return BA_EINVAL;
+    for (int k = 0; k < BA_KT_COUNT; k++) {
+        ms[k] = 0.0;
+        launches[k] = 0;
     }
-    *ms_total = tot;
-    *launches = g_timing.ev.size();
+    int rc = BA_OK;
+    for (auto &r : g_timing.ev) {
+        float t = 0.0f;
+        if (!rc) rc = hip_check(hipEventSynchronize(r.e1));
+        if (!rc) rc = hip_check(hipEventElapsedTime(&t, r.e0, r.e1));
+        ms[r.kind] += t;
+        launches[r.kind]++;
+    }
     timing_release();
     return rc;
 }

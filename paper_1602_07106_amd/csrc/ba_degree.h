@@ -11,7 +11,7 @@
 //   V  (in the generator): the tile flush also writes the second endpoints
 //      alone, 4 bytes per edge, so the partition reads half the bytes of the
 //      edge array.
-//   P  (k_deg_part): persistent blocks read that list in 24K-edge
+//   P  (k_deg_part): persistent blocks read that list in 20K-edge
 //      chunks, counting-sort the second endpoints of a chunk by 32768-node
 //      sub-bucket (v >> 15) in LDS and append each sub-bucket's run of 16-bit
 //      local indices to the block's own region for that sub-bucket.  Regions
@@ -43,8 +43,8 @@ constexpr uint32_t kS2 = 15;                    // sub-bucket width: 32768 nodes
 constexpr uint32_t kSub = 1u << kS2;
 constexpr uint32_t kWin = 2048;                 // sub-buckets per partition window
 constexpr uint32_t kPBlock = 1024;
-constexpr uint32_t kPPer = 24;                  // edges per thread per chunk
-constexpr uint32_t kPChunk = kPBlock * kPPer;   // 24576 edges per chunk
+constexpr uint32_t kPPer = 20;                  // edges per thread per chunk
+constexpr uint32_t kPChunk = kPBlock * kPPer;   // 20480 edges per chunk
 constexpr uint32_t kPBlocksMax = 1024;          // partition blocks a layout allows
 constexpr uint32_t kHPart = 1u << 20;           // entries per count part (target)
 constexpr uint32_t kHBlock = 1024;
@@ -222,13 +222,15 @@ __global__ __launch_bounds__(1024) void k_deg_plan(DegArgs a)
 __global__ __launch_bounds__(kPBlock) void k_deg_part(DegArgs a)
 {
     constexpr uint32_t kOut = kWin << kS2;  // entry outside the window or past the chunk
-    __shared__ uint32_t cnt[kWin];         // per chunk: counts, then cursors
+    __shared__ uint32_t cnt[kWin + 64];    // per chunk: counts, then run starts; + 64 lane-private
+                                           // counters that absorb entries outside the window
     __shared__ uint32_t fill[kWin];        // entries this block has sent to each region
     __shared__ uint32_t cap[kWin];         // region capacity
     __shared__ uint32_t rbase[kWin];       // this block's region start, window-relative
     __shared__ uint2 dl[kWin];             // per chunk: (slot of sorted entry 0, slot limit)
     __shared__ uint32_t stage[kPChunk];    // sorted (bin << 15 | local index)
     __shared__ uint32_t scan_sh[16];
+    __shared__ uint32_t any_over;          // per chunk: some region of this block is full
     const uint32_t g0 = a.g0;
     const uint32_t nwin = min(kWin, a.p.NBsub - g0);
     const uint32_t blk = blockIdx.x, P = gridDim.x;
@@ -241,49 +243,45 @@ __global__ __launch_bounds__(kPBlock) void k_deg_part(DegArgs a)
         rbase[b] = b < nwin ? (uint32_t)(ws_off(a)[g0 + b] - wslot + (uint64_t)blk * cp) : 0u;
     }
 
-    const uint64_t nchunks = (a.p.C + kPChunk - 1) / kPChunk;
+    // whole chunks only: the last C mod kPChunk targets go to k_deg_tail
+    const uint64_t nchunks = a.p.C / kPChunk;
     const uint32_t lane = __lane_id(), wv = threadIdx.x / 64;
     const uint32_t wbase = wv * (kPPer * 64);
-    // second endpoints: wave w reads targets e0 + (24*64) w + 64 q + lane
-    // (64 consecutive 4-byte targets per load).  The next chunk is loaded
-    // while the current one is written out, into the same (by then dead)
-    // registers; whole chunks load unconditionally so that the loads are
-    // issued back to back, only the last, partial chunk tests each index.
-    uint32_t v[kPPer];
+    // second endpoints: wave w reads targets e0 + (20*64) w + 64 q + lane
+    // (64 consecutive 4-byte targets per load, issued back to back).  The
+    // next chunk's loads are issued as soon as the current chunk has moved
+    // to its own registers, so they have a whole chunk's time to arrive.
+    uint32_t v[kPPer], vn[kPPer];
     auto load = [&](uint64_t ch) {
-        const uint64_t e0 = ch * kPChunk;
-        const uint32_t *wsrc = ws_V(a) + e0 + wbase + lane;
-        if (e0 + kPChunk <= a.p.C) {
+        const uint32_t *wsrc = ws_V(a) + ch * kPChunk + wbase + lane;
 #pragma unroll
-            for (uint32_t q = 0; q < kPPer; q++) v[q] = wsrc[q * 64];
-        } else {
-            const uint32_t len = (uint32_t)(a.p.C - e0);
-#pragma unroll
-            for (uint32_t q = 0; q < kPPer; q++) v[q] = wbase + q * 64 + lane < len ? wsrc[q * 64] : 0u;
-        }
+        for (uint32_t q = 0; q < kPPer; q++) vn[q] = wsrc[q * 64];
     };
     if ((uint64_t)blk < nchunks) load(blk);
     for (uint64_t ch = blk; ch < nchunks; ch += P) {
-        const uint64_t e0 = ch * kPChunk;
-        for (uint32_t b = threadIdx.x; b < kWin; b += kPBlock) cnt[b] = 0;
-        if (e0 + kPChunk <= a.p.C) {
 #pragma unroll
-            for (uint32_t q = 0; q < kPPer; q++) {
-                const uint32_t r = (v[q] >> kS2) - g0;
-                v[q] = r < nwin ? (r << kS2) | (v[q] & (kSub - 1)) : kOut;
-            }
-        } else {
-            const uint32_t len = (uint32_t)(a.p.C - e0);
+        for (uint32_t q = 0; q < kPPer; q++) v[q] = vn[q];
+        if (ch + P < nchunks) load(ch + P);
+        for (uint32_t b = threadIdx.x; b < kWin + 64; b += kPBlock) cnt[b] = 0;
 #pragma unroll
-            for (uint32_t q = 0; q < kPPer; q++) {
-                const uint32_t r = (v[q] >> kS2) - g0;
-                v[q] = (wbase + q * 64 + lane < len && r < nwin) ? (r << kS2) | (v[q] & (kSub - 1)) : kOut;
-            }
+        for (uint32_t q = 0; q < kPPer; q++) {
+            const uint32_t r = (v[q] >> kS2) - g0;
+            v[q] = r < nwin ? (r << kS2) | (v[q] & (kSub - 1)) : kOut;
         }
         lds_barrier();
+        // counts; each entry keeps its rank within its bin (16 bits: a bin
+        // holds at most kPChunk entries of a chunk), two ranks a register
+        // (no branches, so the atomics issue back to back)
+        uint32_t rk[kPPer / 2];
 #pragma unroll
-        for (uint32_t q = 0; q < kPPer; q++)
-            if (v[q] != kOut) atomicAdd(&cnt[v[q] >> kS2], 1u);
+        for (uint32_t q = 0; q < kPPer; q += 2) {
+            const uint32_t b0 = (v[q] >> kS2) + (v[q] == kOut ? lane : 0u);
+            const uint32_t b1 = (v[q + 1] >> kS2) + (v[q + 1] == kOut ? lane : 0u);
+            const uint32_t r0 = atomicAdd(&cnt[b0], 1u);
+            const uint32_t r1 = atomicAdd(&cnt[b1], 1u);
+            rk[q / 2] = (r0 & 0xFFFFu) | (r1 << 16);
+        }
+        if (threadIdx.x == 0) any_over = 0;
         lds_barrier();
         // exclusive scan over the window (two bins per thread), destinations
         const uint32_t c0 = cnt[2 * threadIdx.x], c1 = cnt[2 * threadIdx.x + 1];
@@ -299,23 +297,26 @@ __global__ __launch_bounds__(kPBlock) void k_deg_part(DegArgs a)
                 // region slot of sorted entry x is dst + x (mod 2^32), valid while x < lim
                 dl[b] = make_uint2(rbase[b] + f - st, st + min(room, c));
                 fill[b] = f + c;
+                if (c > room) any_over = 1;
             }
-            cnt[b] = st;  // becomes the cursor
+            cnt[b] = st;  // start of the bin's run
         }
         lds_barrier();
-        // scatter into sorted order: eight cursor bumps in flight at a time
+        // scatter into sorted order: run start + rank, four starts read at a time
+        static_assert(kPPer % 4 == 0, "scatter batches");
 #pragma unroll
-        for (uint32_t q0 = 0; q0 < kPPer; q0 += 8) {
-            uint32_t pos[8];
+        for (uint32_t q0 = 0; q0 < kPPer; q0 += 4) {
+            uint32_t st4[4];
 #pragma unroll
-            for (uint32_t j = 0; j < 8; j++)
-                pos[j] = v[q0 + j] != kOut ? atomicAdd(&cnt[v[q0 + j] >> kS2], 1u) : ~0u;
+            for (uint32_t j = 0; j < 4; j++) st4[j] = cnt[v[q0 + j] >> kS2];  // cnt[kWin] for outside entries
 #pragma unroll
-            for (uint32_t j = 0; j < 8; j++)
-                if (pos[j] != ~0u) stage[pos[j]] = v[q0 + j];
+            for (uint32_t j = 0; j < 4; j++) {
+                const uint32_t q = q0 + j;
+                if (v[q] != kOut) stage[st4[j] + ((rk[q / 2] >> (16 * (q & 1))) & 0xFFFFu)] = v[q];
+            }
         }
         lds_barrier();
-        if (ch + P < nchunks) load(ch + P);
+        const bool over = any_over != 0;
         // sorted runs out: consecutive threads take consecutive sorted
         // entries, so a store covers a few runs of contiguous region slots
         for (uint32_t x0 = threadIdx.x; x0 < total; x0 += 4 * kPBlock) {
@@ -325,14 +326,21 @@ __global__ __launch_bounds__(kPBlock) void k_deg_part(DegArgs a)
             for (uint32_t u = 0; u < 4; u++) w[u] = x0 + u * kPBlock < total ? stage[x0 + u * kPBlock] : 0u;
 #pragma unroll
             for (uint32_t u = 0; u < 4; u++) t[u] = dl[w[u] >> kS2];
+            if (!over) {  // no region full in this chunk (the normal case)
 #pragma unroll
-            for (uint32_t u = 0; u < 4; u++) {
-                const uint32_t x = x0 + u * kPBlock;
-                if (x < total) {
-                    if (x < t[u].y)
-                        Lw[t[u].x + x] = (uint16_t)(w[u] & (kSub - 1));
-                    else
-                        deg_atomic_add(a.deg, ((uint64_t)(g0 + (w[u] >> kS2)) << kS2) | (w[u] & (kSub - 1)), 1u);
+                for (uint32_t u = 0; u < 4; u++)
+                    if (x0 + u * kPBlock < total) Lw[t[u].x + x0 + u * kPBlock] = (uint16_t)(w[u] & (kSub - 1));
+            } else {
+#pragma unroll
+                for (uint32_t u = 0; u < 4; u++) {
+                    const uint32_t x = x0 + u * kPBlock;
+                    if (x < total) {
+                        if (x < t[u].y)
+                            Lw[t[u].x + x] = (uint16_t)(w[u] & (kSub - 1));
+                        else
+                            deg_atomic_add(a.deg, ((uint64_t)(g0 + (w[u] >> kS2)) << kS2) | (w[u] & (kSub - 1)),
+                                           1u);
+                    }
                 }
             }
         }
@@ -340,6 +348,15 @@ __global__ __launch_bounds__(kPBlock) void k_deg_part(DegArgs a)
     }
     uint32_t *gfill = ws_fill(a) + (uint64_t)blk * a.p.NBsub + g0;
     for (uint32_t b = threadIdx.x; b < nwin; b += kPBlock) gfill[b] = fill[b];
+}
+
+// The last C mod kPChunk second endpoints of the pass (fewer than one
+// partition chunk), counted with global atomics.
+__global__ __launch_bounds__(256) void k_deg_tail(DegArgs a)
+{
+    const uint64_t e0 = a.p.C / kPChunk * kPChunk;
+    const uint64_t e = e0 + (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < a.p.C) deg_atomic_add(a.deg, ws_V(a)[e], 1u);
 }
 
 // T: per sub-bucket total over its regions (capped fills) and part count.

@@ -121,3 +121,17 @@ def test_binding_refuses_cpu_tensors():
 
     with pytest.raises(ValueError):
         ba.generate(10, 2, 0, device="cpu")
+
+
+def test_timing_kinds_match_header_and_read_empty():
+    src = open(HEADER).read()
+    kinds = dict((k, int(v)) for k, v in re.findall(r"\bBA_KT_(\w+)\s*=\s*(\d+)", src))
+    assert kinds.pop("COUNT") == len(ba.KERNEL_KINDS)
+    assert sorted(kinds.values()) == list(range(len(ba.KERNEL_KINDS)))
+    for name, idx in kinds.items():
+        assert ba.KERNEL_KINDS[idx] == name.lower()
+    ba.kernel_timing(True)
+    got = ba.kernel_timing_read()  # nothing launched: every kind reads zero
+    ba.kernel_timing(False)
+    assert got == {k: (0.0, 0) for k in ba.KERNEL_KINDS}
+    assert ba.lib().ba_kernel_timing_read(None, None) == ba.BA_EINVAL
