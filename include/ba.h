@@ -160,6 +160,68 @@ enum {
 int ba_kernel_timing(int enable);
 int ba_kernel_timing_read(double *ms, uint64_t *launches);
 
+/*
+ * Batched generation: many independent graphs in one persistent launch.
+ * The paper computes every edge independently and hands batches of edge IDs
+ * to processors for load balancing (Section 2, last paragraph); a batch here
+ * is a table of instances j = 0..count-1, each a plain BA graph (n[j], d[j],
+ * seed[j]) whose edge array (the same uint32 pairs ba_generate writes) goes
+ * to edges + out_offset[j] (offsets in uint32 elements).  Instances may be
+ * empty (n or d zero).  Results depend only on each instance's parameters,
+ * never on the batch, its order or the launch shape.
+ *
+ * ba_batch_upload checks the table on the host (BA_ERANGE: an instance with
+ * n > 2^32 or 2*n*d beyond 2^64, or more than 2^40 tiles in all; BA_EINVAL:
+ * null arrays, or a workspace that is null, not 256-byte aligned or smaller
+ * than ba_batch_workspace_bytes(count)), writes the device table into the
+ * caller's workspace and waits for that copy (the host arrays may be freed on
+ * return).  It fills *info (host memory, caller-owned), including
+ * info->edges_len, the uint32 elements the output must hold.
+ *
+ * ba_batch_launch enqueues the whole batch on `stream` as one kernel launch
+ * (no copy, no allocation: it can be captured into a HIP graph).  Outputs of
+ * different instances must not overlap; edges must be 4-byte aligned and hold
+ * edges_len >= info->edges_len elements, else BA_EINVAL.  The workspace must
+ * stay untouched while launches that use it run.
+ *
+ * ba_batch_autotune times every kernel shape (tile edges x waves per block,
+ * shapes 0..BA_BATCH_SHAPES-1) on the given batch and keeps the fastest for
+ * the current device; later ba_batch_launch calls on that device use it
+ * (ba_batch_current_shape reports its index, ba_batch_shape_dims the tile
+ * and block of any index).  Without tuning the shape is 0: 2048-edge tiles,
+ * 4 waves per block.  The tuner's own launches write the batch's edges too.
+ * ba_batch_launch_shape launches with an explicit shape (same output).
+ *
+ * ba_batch_plan_rounds (host only) splits a table, in order, into rounds
+ * whose outputs fit round_elems uint32 elements each, for tables whose
+ * whole output exceeds device memory: round_of[j] and offset_of[j] (host
+ * arrays of count) give each instance's round and 16-byte-aligned offset in
+ * its round's buffer; *rounds the number of rounds.  BA_EINVAL when a single
+ * instance needs more than round_elems.
+ */
+typedef struct {
+    uint32_t count;
+    uint32_t reserved;
+    uint64_t tiles[3];   /* tiles of 1024, 2048 and 4096 edges */
+    uint64_t edges_len;  /* uint32 elements the output must hold */
+} ba_batch_info;
+
+uint64_t ba_batch_workspace_bytes(uint32_t count);
+int ba_batch_upload(uint32_t count, const uint64_t *n, const uint32_t *d, const uint64_t *seed,
+                    const uint64_t *out_offset, void *workspace, uint64_t workspace_bytes,
+                    ba_batch_info *info, void *stream);
+int ba_batch_launch(const ba_batch_info *info, const void *workspace, uint32_t *edges,
+                    uint64_t edges_len, void *stream);
+int ba_batch_autotune(const ba_batch_info *info, const void *workspace, uint32_t *edges,
+                      uint64_t edges_len, int *shape_out, void *stream);
+int ba_batch_launch_shape(const ba_batch_info *info, const void *workspace, uint32_t *edges,
+                          uint64_t edges_len, int shape, void *stream);
+enum { BA_BATCH_SHAPES = 5 };
+int ba_batch_current_shape(int *shape);
+int ba_batch_shape_dims(int shape, int *tile_edges, int *waves_per_block);
+int ba_batch_plan_rounds(uint32_t count, const uint64_t *n, const uint32_t *d, uint64_t round_elems,
+                         uint32_t *round_of, uint64_t *offset_of, uint32_t *rounds);
+
 /* Text for a status code (static storage, never NULL). */
 const char *ba_strerror(int status);
 

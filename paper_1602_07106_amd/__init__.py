@@ -20,8 +20,9 @@ from __future__ import annotations
 
 import ctypes
 import os
-from typing import Dict, Optional, Tuple
+from typing import Dict, Optional, Sequence, Tuple
 
+import numpy as np
 import torch
 
 from . import build as _build
@@ -38,6 +39,10 @@ __all__ = [
     "kernel_timing_read",
     "degrees",
     "degrees_range",
+    "Batch",
+    "batch_plan_rounds",
+    "batch_shape",
+    "generate_batch",
     "lib",
     "library_path",
 ]
@@ -72,6 +77,14 @@ _SIGS = {
     "ba_host_divide": (_int, [_u32, _p, _p, _u64]),
     "ba_kernel_timing": (_int, [_int]),
     "ba_kernel_timing_read": (_int, [_p, _p]),
+    "ba_batch_workspace_bytes": (_u64, [_u32]),
+    "ba_batch_upload": (_int, [_u32, _p, _p, _p, _p, _p, _u64, _p, _p]),
+    "ba_batch_launch": (_int, [_p, _p, _p, _u64, _p]),
+    "ba_batch_autotune": (_int, [_p, _p, _p, _u64, _p, _p]),
+    "ba_batch_launch_shape": (_int, [_p, _p, _p, _u64, _int, _p]),
+    "ba_batch_current_shape": (_int, [_p]),
+    "ba_batch_shape_dims": (_int, [_int, _p, _p]),
+    "ba_batch_plan_rounds": (_int, [_u32, _p, _p, _u64, _p, _p, _p]),
 }
 
 _lib = None
@@ -275,3 +288,124 @@ def degrees_range(
             "ba_degrees_range",
             lib().ba_degrees_range(n, d, seed, begin, count, first_k, _ptr(deg), _ptr(cs), _stream(dev)),
         )
+
+
+class BatchInfo(ctypes.Structure):
+    """ba_batch_info of include/ba.h."""
+
+    _fields_ = [
+        ("count", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("tiles", ctypes.c_uint64 * 3),
+        ("edges_len", ctypes.c_uint64),
+    ]
+
+
+def _table(n: Sequence[int], d: Sequence[int], seed: Optional[Sequence[int]] = None):
+    nn = np.ascontiguousarray(np.asarray(n, dtype=np.uint64))
+    dd = np.ascontiguousarray(np.asarray(d, dtype=np.uint32))
+    if nn.shape != dd.shape or nn.ndim != 1:
+        raise ValueError("n and d must be 1-D and of equal length")
+    ss = None
+    if seed is not None:
+        ss = np.ascontiguousarray(np.asarray(seed, dtype=np.uint64))
+        if ss.shape != nn.shape:
+            raise ValueError("seed must match n")
+    return nn, dd, ss
+
+
+def batch_plan_rounds(n: Sequence[int], d: Sequence[int], round_elems: int) -> Tuple[np.ndarray, np.ndarray, int]:
+    """(round_of, offset_of, rounds): the instances, in order, packed into
+    rounds whose edge outputs fit round_elems uint32 each (see
+    ba_batch_plan_rounds).  Also the packed layout of a single round."""
+    nn, dd, _ = _table(n, d)
+    r = np.zeros(nn.size, dtype=np.uint32)
+    o = np.zeros(nn.size, dtype=np.uint64)
+    k = ctypes.c_uint32(0)
+    _check("ba_batch_plan_rounds", lib().ba_batch_plan_rounds(nn.size, nn.ctypes.data, dd.ctypes.data, round_elems,
+                                                                r.ctypes.data, o.ctypes.data, ctypes.addressof(k)))
+    return r, o, k.value
+
+
+class Batch:
+    """A table of instances (n[j], d[j], seed[j]) uploaded to the device.
+    Instance j writes its uint32 edge pairs at out_offset[j] (uint32
+    elements) of the output; by default the instances are packed in order,
+    each 16-byte aligned."""
+
+    def __init__(self, n, d, seed, out_offset=None, device=None):
+        nn, dd, ss = _table(n, d, seed)
+        if out_offset is None:
+            _, out_offset, _ = batch_plan_rounds(nn, dd, (1 << 64) - 1)
+        oo = np.ascontiguousarray(np.asarray(out_offset, dtype=np.uint64))
+        if oo.shape != nn.shape:
+            raise ValueError("out_offset must match n")
+        self.count = nn.size
+        self.out_offset = oo
+        self.ws = torch.empty(max(1, int(lib().ba_batch_workspace_bytes(self.count))), dtype=torch.uint8,
+                              device=_device(device))
+        self.device = self.ws.device  # with its index
+        self.info = BatchInfo()
+        with torch.cuda.device(self.device):
+            _check("ba_batch_upload",
+                   lib().ba_batch_upload(self.count, nn.ctypes.data, dd.ctypes.data, ss.ctypes.data, oo.ctypes.data,
+                                         self.ws.data_ptr(), self.ws.numel(), ctypes.addressof(self.info),
+                                         _stream(self.device)))
+        self.edges_len = int(self.info.edges_len)
+
+    def empty_output(self) -> torch.Tensor:
+        return torch.empty(max(1, self.edges_len), dtype=torch.int32, device=self.device)
+
+    def _out(self, out: torch.Tensor) -> Tuple[int, int]:
+        if out.dtype != torch.int32 or out.device != self.device or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int32 tensor on the batch's device")
+        return out.data_ptr(), out.numel()
+
+    def launch(self, out: torch.Tensor, shape: Optional[int] = None) -> torch.Tensor:
+        """Every instance's edges into out (int32, at least edges_len), with
+        the device's tuned kernel shape or an explicit one."""
+        p, ln = self._out(out)
+        with torch.cuda.device(self.device):
+            if shape is None:
+                _check("ba_batch_launch", lib().ba_batch_launch(ctypes.addressof(self.info), self.ws.data_ptr(), p, ln,
+                                                                _stream(self.device)))
+            else:
+                _check("ba_batch_launch_shape",
+                       lib().ba_batch_launch_shape(ctypes.addressof(self.info), self.ws.data_ptr(), p, ln, shape,
+                                                   _stream(self.device)))
+        return out
+
+    def autotune(self, out: torch.Tensor) -> int:
+        """Time every kernel shape on this batch and keep the fastest for the
+        device (see ba_batch_autotune); returns the chosen shape index."""
+        p, ln = self._out(out)
+        shape = ctypes.c_int(-1)
+        with torch.cuda.device(self.device):
+            _check("ba_batch_autotune", lib().ba_batch_autotune(ctypes.addressof(self.info), self.ws.data_ptr(), p, ln,
+                                                                ctypes.addressof(shape), _stream(self.device)))
+        return shape.value
+
+
+BATCH_SHAPES = 5
+
+
+def batch_shape(shape: Optional[int] = None) -> Tuple[int, int, int]:
+    """(index, tile edges, waves per block) of a kernel shape; by default the
+    one ba_batch_launch uses on the current device."""
+    if shape is None:
+        k = ctypes.c_int(0)
+        _check("ba_batch_current_shape", lib().ba_batch_current_shape(ctypes.addressof(k)))
+        shape = k.value
+    t, w = ctypes.c_int(0), ctypes.c_int(0)
+    _check("ba_batch_shape_dims", lib().ba_batch_shape_dims(shape, ctypes.addressof(t), ctypes.addressof(w)))
+    return shape, t.value, w.value
+
+
+def generate_batch(n, d, seed, *, out_offset=None, out: Optional[torch.Tensor] = None, device=None):
+    """(edges, out_offset): every instance's uint32 edge pairs in one int32
+    tensor, instance j at out_offset[j] (packed by default)."""
+    b = Batch(n, d, seed, out_offset, device if out is None else out.device)
+    if out is None:
+        out = b.empty_output()
+    b.launch(out)
+    return out, b.out_offset

@@ -4,6 +4,7 @@
 """
 from __future__ import annotations
 
+import glob
 import os
 import subprocess
 import sys
@@ -11,7 +12,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "ba.hip")
-DEPS = [SRC, os.path.join(PKG, "csrc", "ba_device.h"), os.path.join(ROOT, "include", "ba.h")]
+DEPS = [SRC, os.path.join(ROOT, "include", "ba.h")] + sorted(glob.glob(os.path.join(PKG, "csrc", "*.h")))
 LIB = os.path.join(PKG, "libba.so")
 ARCH = "gfx950"
 

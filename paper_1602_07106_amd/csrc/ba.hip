@@ -196,6 +196,12 @@ __global__ __launch_bounds__(kGenBlock) void k_gen_u32(GenArgs a)
     }
 }
 
+}  // namespace ba
+
+#include "ba_batch.h"
+
+namespace ba {
+
 // 64-bit node IDs, any positions: each finished chain stores its edge pair
 // directly (used for ranges of very large graphs; not the bandwidth path).
 struct Gen64Args {
@@ -619,6 +625,82 @@ static int launch_stream(uint64_t begin, uint64_t count, uint32_t d, uint64_t se
     return narrow ? launch_stream_one<true>(a, st) : launch_stream_one<false>(a, st);
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched generation: device table layout, upload, launch, tile-shape tuning.
+
+struct BatchLayout {
+    uint64_t o_inst, o_tile0[3], bytes;
+};
+
+static BatchLayout batch_layout(uint32_t count)
+{
+    BatchLayout L{};
+    uint64_t o = 0;
+    L.o_inst = o;
+    o = align256(o + sizeof(BatchInst) * (uint64_t)count);
+    for (int s = 0; s < 3; s++) {
+        L.o_tile0[s] = o;
+        o = align256(o + 8ull * ((uint64_t)count + 1));
+    }
+    L.bytes = o;
+    return L;
+}
+
+// Kernel shapes the tuner chooses from: (tile edges, waves per block).
+struct BatchShape {
+    int tile_idx;  // index into kBatchTiles
+    uint32_t waves;
+};
+constexpr BatchShape kBatchShapes[] = {{1, 4}, {0, 4}, {2, 4}, {0, 8}, {1, 8}};
+constexpr int kBatchShapeCount = sizeof(kBatchShapes) / sizeof(kBatchShapes[0]);
+constexpr int kMaxDevices = 64;
+// Chosen shape per device: written only by ba_batch_autotune, -1 = default (shape 0).
+static int g_batch_shape[kMaxDevices] = {
+    -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
+    -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
+    -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+
+template <uint32_t TILE, uint32_t WAVES>
+static int launch_batch_shape(BatchArgs a, hipStream_t st)
+{
+    uint32_t grid = 0;
+    int rc = persistent_grid(k_gen_batch<TILE, WAVES>, WAVES * 64, &grid);
+    if (rc) return rc;
+    return launch_timed(BA_KT_GEN, st,
+                        [&] { hipLaunchKernelGGL((k_gen_batch<TILE, WAVES>), dim3(grid), dim3(WAVES * 64), 0, st, a); });
+}
+
+static int launch_batch(int shape, const ba_batch_info *info, const void *ws, uint32_t *edges, hipStream_t st)
+{
+    const BatchShape S = kBatchShapes[shape];
+    const BatchLayout L = batch_layout(info->count);
+    BatchArgs a{};
+    a.inst = (const BatchInst *)((const unsigned char *)ws + L.o_inst);
+    a.tile0 = (const uint64_t *)((const unsigned char *)ws + L.o_tile0[S.tile_idx]);
+    a.count = info->count;
+    a.tiles = info->tiles[S.tile_idx];
+    a.edges = edges;
+    if (a.tiles == 0) return BA_OK;
+    switch (shape) {
+    case 0: return launch_batch_shape<2048, 4>(a, st);
+    case 1: return launch_batch_shape<1024, 4>(a, st);
+    case 2: return launch_batch_shape<4096, 4>(a, st);
+    case 3: return launch_batch_shape<1024, 8>(a, st);
+    default: return launch_batch_shape<2048, 8>(a, st);
+    }
+}
+
+static int current_device_slot(int *slot)
+{
+    int dev = 0;
+    int rc = hip_check(hipGetDevice(&dev));
+    if (rc) return rc;
+    if (dev < 0 || dev >= kMaxDevices) return BA_EINVAL;
+    *slot = dev;
+    return BA_OK;
+}
+
 }  // namespace ba
 
 using namespace ba;
@@ -768,6 +850,157 @@ int ba_degrees(uint64_t n, uint32_t d, uint64_t seed, uint64_t first_k, uint64_t
         if (rc) return rc;
     }
     return ba_degrees_range(n, d, seed, 0, m, first_k, deg, xor_checksum, stream);
+}
+
+uint64_t ba_batch_workspace_bytes(uint32_t count) { return batch_layout(count).bytes; }
+
+int ba_batch_upload(uint32_t count, const uint64_t *n, const uint32_t *d, const uint64_t *seed,
+                    const uint64_t *out_offset, void *workspace, uint64_t workspace_bytes, ba_batch_info *info,
+                    void *stream)
+{
+    if (!info || (count && (!n || !d || !seed || !out_offset))) return BA_EINVAL;
+    const BatchLayout L = batch_layout(count);
+    if (count && (!workspace || ((uintptr_t)workspace & 255) || workspace_bytes < L.bytes)) return BA_EINVAL;
+    std::vector<unsigned char> host(L.bytes, 0);
+    BatchInst *I = (BatchInst *)(host.data() + L.o_inst);
+    uint64_t *T[3];
+    for (int s = 0; s < 3; s++) T[s] = (uint64_t *)(host.data() + L.o_tile0[s]);
+    uint64_t tiles[3] = {0, 0, 0}, need = 0;
+    for (uint32_t j = 0; j < count; j++) {
+        uint64_t m;
+        if (!graph_fits(n[j], d[j], &m) || n[j] > ((uint64_t)1 << 32)) return BA_ERANGE;
+        const uint64_t end = out_offset[j] + 2 * m;
+        if (end < out_offset[j]) return BA_ERANGE;
+        if (m && end > need) need = end;
+        I[j].key = make_hash_key(seed[j]);
+        I[j].narrow = 2 * m <= ((uint64_t)1 << 32) ? 1u : 0u;
+        I[j].div = make_divider(d[j] ? d[j] : 1u);
+        I[j].m = m;
+        I[j].out = out_offset[j];
+        for (int s = 0; s < 3; s++) {
+            T[s][j] = tiles[s];
+            tiles[s] += (m + kBatchTiles[s] - 1) / kBatchTiles[s];
+        }
+    }
+    // tiles * waves must fit 64 bits in the kernel's split of the tiles
+    if (tiles[0] >= ((uint64_t)1 << 40)) return BA_ERANGE;
+    for (int s = 0; s < 3; s++) T[s][count] = tiles[s];
+    if (count) {
+        hipStream_t st = (hipStream_t)stream;
+        int rc = hip_check(hipMemcpyAsync(workspace, host.data(), L.bytes, hipMemcpyHostToDevice, st));
+        if (rc) return rc;
+        if ((rc = hip_check(hipStreamSynchronize(st)))) return rc;
+    }
+    info->count = count;
+    info->reserved = 0;
+    for (int s = 0; s < 3; s++) info->tiles[s] = tiles[s];
+    info->edges_len = need;
+    return BA_OK;
+}
+
+int ba_batch_launch(const ba_batch_info *info, const void *workspace, uint32_t *edges, uint64_t edges_len,
+                    void *stream)
+{
+    if (!info) return BA_EINVAL;
+    if (info->count == 0 || info->tiles[0] == 0) return BA_OK;
+    if (!workspace || !edges || ((uintptr_t)edges & 3) || edges_len < info->edges_len) return BA_EINVAL;
+    int slot = 0;
+    int rc = current_device_slot(&slot);
+    if (rc) return rc;
+    const int shape = g_batch_shape[slot] < 0 ? 0 : g_batch_shape[slot];
+    return launch_batch(shape, info, workspace, edges, (hipStream_t)stream);
+}
+
+int ba_batch_autotune(const ba_batch_info *info, const void *workspace, uint32_t *edges, uint64_t edges_len,
+                      int *shape_out, void *stream)
+{
+    if (!info) return BA_EINVAL;
+    if (info->count == 0 || info->tiles[0] == 0) return BA_EINVAL;
+    if (!workspace || !edges || ((uintptr_t)edges & 3) || edges_len < info->edges_len) return BA_EINVAL;
+    int slot = 0;
+    int rc = current_device_slot(&slot);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if ((rc = hip_check(hipEventCreate(&e0)))) return rc;
+    if ((rc = hip_check(hipEventCreate(&e1)))) {
+        (void)hipEventDestroy(e0);
+        return rc;
+    }
+    int best = 0;
+    float best_ms = 0.0f;
+    const bool timing = g_timing.on;
+    g_timing.on = false;  // the tuner's own launches stay out of the kernel timing
+    for (int s = 0; s < kBatchShapeCount && !rc; s++) {
+        rc = launch_batch(s, info, workspace, edges, st);  // warm-up
+        if (!rc) rc = hip_check(hipEventRecord(e0, st));
+        for (int k = 0; k < 2 && !rc; k++) rc = launch_batch(s, info, workspace, edges, st);
+        if (!rc) rc = hip_check(hipEventRecord(e1, st));
+        if (!rc) rc = hip_check(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1));
+        if (!rc && (s == 0 || ms < best_ms)) {
+            best = s;
+            best_ms = ms;
+        }
+    }
+    g_timing.on = timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    g_batch_shape[slot] = best;
+    if (shape_out) *shape_out = best;
+    return BA_OK;
+}
+
+int ba_batch_launch_shape(const ba_batch_info *info, const void *workspace, uint32_t *edges, uint64_t edges_len,
+                          int shape, void *stream)
+{
+    if (!info || shape < 0 || shape >= kBatchShapeCount) return BA_EINVAL;
+    if (info->count == 0 || info->tiles[0] == 0) return BA_OK;
+    if (!workspace || !edges || ((uintptr_t)edges & 3) || edges_len < info->edges_len) return BA_EINVAL;
+    return launch_batch(shape, info, workspace, edges, (hipStream_t)stream);
+}
+
+int ba_batch_current_shape(int *shape)
+{
+    if (!shape) return BA_EINVAL;
+    int slot = 0;
+    int rc = current_device_slot(&slot);
+    if (rc) return rc;
+    *shape = g_batch_shape[slot] < 0 ? 0 : g_batch_shape[slot];
+    return BA_OK;
+}
+
+int ba_batch_shape_dims(int shape, int *tile_edges, int *waves_per_block)
+{
+    if (shape < 0 || shape >= kBatchShapeCount || !tile_edges || !waves_per_block) return BA_EINVAL;
+    *tile_edges = (int)kBatchTiles[kBatchShapes[shape].tile_idx];
+    *waves_per_block = (int)kBatchShapes[shape].waves;
+    return BA_OK;
+}
+
+int ba_batch_plan_rounds(uint32_t count, const uint64_t *n, const uint32_t *d, uint64_t round_elems,
+                         uint32_t *round_of, uint64_t *offset_of, uint32_t *rounds)
+{
+    if (!rounds || (count && (!n || !d || !round_of || !offset_of))) return BA_EINVAL;
+    uint32_t r = 0;
+    uint64_t off = 0;
+    for (uint32_t j = 0; j < count; j++) {
+        uint64_t m;
+        if (!graph_fits(n[j], d[j], &m) || n[j] > ((uint64_t)1 << 32)) return BA_ERANGE;
+        const uint64_t need = (2 * m + 3) & ~(uint64_t)3;  // each instance starts 16-byte aligned
+        if (need > round_elems) return BA_EINVAL;
+        if (off + need > round_elems) {
+            r++;
+            off = 0;
+        }
+        round_of[j] = r;
+        offset_of[j] = off;
+        off += need;
+    }
+    *rounds = count ? r + 1 : 0;
+    return BA_OK;
 }
 
 const char *ba_strerror(int status)

@@ -1,0 +1,108 @@
+// ba_batch.h -- many independent graphs in one persistent launch (gfx950).
+//
+// A batch is a ragged table of instances (n_j, d_j, seed_j), each with its
+// own edge array at its own offset of one output buffer.  The paper hands
+// edge-ID batches to processors for load balancing (Section 2, last
+// paragraph); here the unit handed out is a tile of consecutive edges of one
+// instance, and the tiles of all instances are numbered one after the other
+// so that one launch covers the whole table.  Every tile runs the same
+// lane-refill chain loop as the single-graph generator, with the instance's
+// own key and divider.
+//
+// Included by ba.hip after the chain loop and the pair stores.
+#pragma once
+
+namespace ba {
+
+// One instance of a batch in device memory (64 bytes).
+struct BatchInst {
+    HashKey key;
+    uint32_t narrow;  // 1 when every position 2m-1 of the instance is below 2^32
+    Divider div;
+    uint64_t m;       // edges
+    uint64_t out;     // offset (uint32 elements) of its edge array in the output
+    uint64_t pad;
+};
+static_assert(sizeof(BatchInst) == 64, "BatchInst layout");
+
+struct BatchArgs {
+    const BatchInst *inst;  // count entries
+    const uint64_t *tile0;  // count + 1 entries: first tile of each instance, tile0[count] = tiles
+    uint32_t count;
+    uint64_t tiles;
+    uint32_t *edges;
+};
+
+// Tile sizes a batch layout is prepared for (the launch picks one).
+constexpr uint32_t kBatchTiles[3] = {1024, 2048, 4096};
+
+// Wave w of W takes the contiguous tiles [T w / W, T (w+1) / W), so its
+// instance index only moves forward; one binary search per wave finds the
+// first.  Empty instances (m = 0) own no tile and are skipped.
+template <uint32_t TILE, uint32_t WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_gen_batch(BatchArgs a)
+{
+    __shared__ uint32_t stage_all[WAVES][TILE];
+    const uint32_t lane = __lane_id();
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    uint32_t *stage = stage_all[wv];
+    const uint64_t W = (uint64_t)gridDim.x * WAVES, w = (uint64_t)blockIdx.x * WAVES + wv;
+    const uint64_t t0 = a.tiles * w / W, t1 = a.tiles * (w + 1) / W;
+    if (t0 >= t1) return;
+    uint32_t lo = 0, hi = a.count;  // tile0[lo] <= t0 < tile0[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (a.tile0[mid] <= t0) lo = mid; else hi = mid;
+    }
+    uint32_t j = lo;
+    uint64_t tcur = a.tile0[j], tnext = a.tile0[j + 1];
+    BatchInst I = a.inst[j];
+    for (uint64_t t = t0; t < t1; t++) {
+        while (t >= tnext) {
+            j++;
+            tcur = tnext;
+            tnext = a.tile0[j + 1];
+            I = a.inst[j];
+        }
+        const uint64_t off = (t - tcur) * TILE;
+        const uint32_t tn = (uint32_t)min((uint64_t)TILE, I.m - off);
+        if (I.narrow)
+            chain_tile(stage, tn, lane, (uint32_t)(2 * off + 1), [&](uint32_t r) { return hash_narrow(r, I.key); },
+                       [](uint32_t r) { return r >> 1; });
+        else
+            chain_tile(stage, tn, lane, 2 * off + 1, [&](uint64_t r) { return hash_wide(r, I.key); },
+                       [&](uint64_t r) { return (uint32_t)div64(r >> 1, I.div); });
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+        uint32_t *out = a.edges + I.out + 2 * off;
+        const bool vec16 = (((uintptr_t)(a.edges + I.out)) & 15) == 0;  // off is a multiple of 2 edges
+        for (uint32_t jj = 2 * lane; jj < tn; jj += 2 * kWave) {
+            const uint2 s = *reinterpret_cast<const uint2 *>(stage + jj);
+            uint32_t u0, u1, v0, v1;
+            if (I.narrow) {
+                const uint32_t i0 = (uint32_t)off + jj;
+                u0 = div32(i0, I.div);
+                u1 = div32(i0 + 1, I.div);
+                v0 = div32(s.x, I.div);
+                v1 = div32(s.y, I.div);
+            } else {
+                const uint64_t i0 = off + jj;
+                u0 = (uint32_t)div64(i0, I.div);
+                u1 = (uint32_t)div64(i0 + 1, I.div);
+                v0 = s.x;
+                v1 = s.y;
+            }
+            if (vec16)
+                store_pair<true>(out, jj, tn, u0, v0, u1, v1);
+            else
+                store_pair<false>(out, jj, tn, u0, v0, u1, v1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+}  // namespace ba

@@ -135,3 +135,42 @@ def test_timing_kinds_match_header_and_read_empty():
     ba.kernel_timing(False)
     assert got == {k: (0.0, 0) for k in ba.KERNEL_KINDS}
     assert ba.lib().ba_kernel_timing_read(None, None) == ba.BA_EINVAL
+
+
+def test_batch_round_planning():
+    n = [1000, 5, 0, 7, 300, 2]
+    d = [3, 2, 4, 1, 2, 9]
+    r, o, k = ba.batch_plan_rounds(n, d, 7000)
+    m2 = [2 * a * b for a, b in zip(n, d)]
+    assert k == 2 and r.tolist() == [0, 0, 0, 0, 1, 1]
+    assert all(int(x) % 4 == 0 for x in o)  # 16-byte aligned starts
+    for rr in range(k):  # inside a round: in order, disjoint, within the budget
+        js = [j for j in range(len(n)) if r[j] == rr]
+        for a, b in zip(js, js[1:]):
+            assert int(o[a]) + m2[a] <= int(o[b])
+        assert int(o[js[-1]]) + m2[js[-1]] <= 7000
+    with pytest.raises(ba.BAError):
+        ba.batch_plan_rounds([1000], [3], 5999)  # one instance bigger than a round
+    with pytest.raises(ba.BAError):
+        ba.batch_plan_rounds([(1 << 32) + 1], [1], 1 << 40)  # uint32 IDs need n <= 2^32
+    assert ba.batch_plan_rounds([], [], 10)[2] == 0
+
+
+def test_batch_host_validation_without_gpu():
+    L = ba.lib()
+    info = ba.BatchInfo()
+    assert L.ba_batch_upload(0, None, None, None, None, None, 0, ctypes.addressof(info), None) == ba.BA_OK
+    assert info.count == 0 and info.edges_len == 0
+    assert L.ba_batch_launch(ctypes.addressof(info), None, None, 0, None) == ba.BA_OK  # empty batch: no-op
+    assert L.ba_batch_upload(1, None, None, None, None, None, 0, ctypes.addressof(info), None) == ba.BA_EINVAL
+    nn = np.array([(1 << 32) + 1], dtype=np.uint64)
+    dd = np.array([1], dtype=np.uint32)
+    ss = np.array([0], dtype=np.uint64)
+    oo = np.array([0], dtype=np.uint64)
+    # a workspace that is too small is refused before any device work
+    assert L.ba_batch_upload(1, nn.ctypes.data, dd.ctypes.data, ss.ctypes.data, oo.ctypes.data, 256, 1,
+                             ctypes.addressof(info), None) == ba.BA_EINVAL
+    assert L.ba_batch_workspace_bytes(4096) >= 4096 * 64 + 3 * 4097 * 8
+    assert L.ba_batch_launch_shape(ctypes.addressof(info), None, None, 0, 5, None) == ba.BA_EINVAL
+    assert [ba.batch_shape(k)[1:] for k in range(ba.BATCH_SHAPES)] == [(2048, 4), (1024, 4), (4096, 4), (1024, 8),
+                                                                       (2048, 8)]
