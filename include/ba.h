@@ -222,6 +222,57 @@ int ba_batch_shape_dims(int shape, int *tile_edges, int *waves_per_block);
 int ba_batch_plan_rounds(uint32_t count, const uint64_t *n, const uint32_t *d, uint64_t round_elems,
                          uint32_t *round_of, uint64_t *offset_of, uint32_t *rounds);
 
+/*
+ * Served generation: continuous batching of requests on one stream.
+ * A request is a plain BA graph (n, d, seed) and asks either for its whole
+ * edge array (kind BA_REQ_EDGES: uint32 pairs as ba_generate writes them,
+ * 8*n*d bytes) or for the streamed first-k degrees and edge checksum of
+ * ba_degrees (kind BA_REQ_DEGREES: first_k uint64 counts then the uint64
+ * checksum, 8*(first_k+1) bytes).  Results are bit-identical to the same
+ * request run alone.
+ *
+ * ba_server_create takes a caller-owned device arena (256-byte aligned, at
+ * least 4 KiB; results and batch tables live there) and a stream, and
+ * records the server's time origin on that stream.  ba_server_submit
+ * queues a request on the host (BA_ERANGE / BA_EINVAL for graphs the
+ * matching call refuses) and returns its ticket.  ba_server_pump retires
+ * finished steps and, when fewer than max_inflight steps are in flight,
+ * launches one more: it admits queued requests in arrival order while their
+ * outputs fit the free arena (admission by HBM bytes), runs every admitted
+ * edge request as one batched persistent launch and every degree request
+ * as a streaming launch, and records one event for the step (*launched =
+ * requests admitted).  It never blocks on the GPU.  A request that cannot
+ * fit even an empty arena is marked BA_JOB_FAILED.
+ * ba_server_poll reports a ticket's state and, once BA_JOB_READY, the GPU
+ * completion time of its step in ms after the time origin and the byte
+ * offset/size of its result in the arena.  ba_server_completed hands out
+ * (up to capacity) the tickets that became ready or failed since its last
+ * call, oldest first, so a client need not poll every ticket.
+ * ba_server_release returns a ready result's arena space.  ba_server_destroy waits for the stream and
+ * frees the server (not the arena).  One host thread per server; calls on
+ * one server must not overlap.
+ */
+enum { BA_REQ_EDGES = 0, BA_REQ_DEGREES = 1 };
+enum { BA_JOB_QUEUED = 0, BA_JOB_RUNNING = 1, BA_JOB_READY = 2, BA_JOB_FAILED = 3, BA_JOB_RELEASED = 4 };
+typedef struct {
+    uint64_t n;
+    uint64_t seed;
+    uint64_t first_k;  /* BA_REQ_DEGREES: nodes 0..first_k-1 (first_k <= n) */
+    uint32_t d;
+    uint32_t kind;     /* BA_REQ_EDGES or BA_REQ_DEGREES */
+} ba_request;
+typedef struct ba_server ba_server;
+
+int ba_server_create(void *arena, uint64_t arena_bytes, void *stream, ba_server **out);
+int ba_server_destroy(ba_server *s);
+int ba_server_submit(ba_server *s, const ba_request *r, uint64_t *ticket);
+int ba_server_pump(ba_server *s, uint32_t max_inflight, uint32_t *launched);
+int ba_server_poll(ba_server *s, uint64_t ticket, int *state, double *done_ms, uint64_t *offset,
+                   uint64_t *bytes);
+int ba_server_completed(ba_server *s, uint64_t *tickets, uint32_t capacity, uint32_t *count);
+int ba_server_release(ba_server *s, uint64_t ticket);
+int ba_server_stats(ba_server *s, uint64_t *queued, uint32_t *inflight, uint64_t *arena_used);
+
 /* Text for a status code (static storage, never NULL). */
 const char *ba_strerror(int status);
 

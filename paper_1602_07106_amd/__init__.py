@@ -43,6 +43,7 @@ __all__ = [
     "batch_plan_rounds",
     "batch_shape",
     "generate_batch",
+    "Server",
     "lib",
     "library_path",
 ]
@@ -85,6 +86,14 @@ _SIGS = {
     "ba_batch_current_shape": (_int, [_p]),
     "ba_batch_shape_dims": (_int, [_int, _p, _p]),
     "ba_batch_plan_rounds": (_int, [_u32, _p, _p, _u64, _p, _p, _p]),
+    "ba_server_create": (_int, [_p, _u64, _p, _p]),
+    "ba_server_destroy": (_int, [_p]),
+    "ba_server_submit": (_int, [_p, _p, _p]),
+    "ba_server_pump": (_int, [_p, _u32, _p]),
+    "ba_server_poll": (_int, [_p, _u64, _p, _p, _p, _p]),
+    "ba_server_completed": (_int, [_p, _p, _u32, _p]),
+    "ba_server_release": (_int, [_p, _u64]),
+    "ba_server_stats": (_int, [_p, _p, _p, _p]),
 }
 
 _lib = None
@@ -409,3 +418,98 @@ def generate_batch(n, d, seed, *, out_offset=None, out: Optional[torch.Tensor] =
         out = b.empty_output()
     b.launch(out)
     return out, b.out_offset
+
+
+REQ_EDGES, REQ_DEGREES = 0, 1
+JOB_QUEUED, JOB_RUNNING, JOB_READY, JOB_FAILED, JOB_RELEASED = 0, 1, 2, 3, 4
+
+
+class Request(ctypes.Structure):
+    """ba_request of include/ba.h."""
+
+    _fields_ = [
+        ("n", ctypes.c_uint64),
+        ("seed", ctypes.c_uint64),
+        ("first_k", ctypes.c_uint64),
+        ("d", ctypes.c_uint32),
+        ("kind", ctypes.c_uint32),
+    ]
+
+
+class Server:
+    """Continuous batching of generation requests on one stream (see
+    ba_server_* in include/ba.h).  Results live in a device arena of
+    arena_bytes until released."""
+
+    def __init__(self, arena_bytes: int, device=None, stream: Optional[torch.cuda.Stream] = None):
+        dev = _device(device)
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
+        self.device = self.arena.device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check("ba_server_create", lib().ba_server_create(self.arena.data_ptr(), arena_bytes,
+                                                              self.stream.cuda_stream, ctypes.addressof(h)))
+        self._h = h
+
+    def close(self) -> None:
+        if self._h:
+            _check("ba_server_destroy", lib().ba_server_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit_edges(self, n: int, d: int, seed: int) -> int:
+        return self._submit(Request(n, seed, 0, d, REQ_EDGES))
+
+    def submit_degrees(self, n: int, d: int, seed: int, first_k: int) -> int:
+        return self._submit(Request(n, seed, first_k, d, REQ_DEGREES))
+
+    def _submit(self, r: Request) -> int:
+        t = ctypes.c_uint64(0)
+        _check("ba_server_submit", lib().ba_server_submit(self._h, ctypes.addressof(r), ctypes.addressof(t)))
+        return t.value
+
+    def pump(self, max_inflight: int = 2) -> int:
+        """Retire finished steps; launch one more when fewer than max_inflight
+        are in flight.  Returns the number of requests admitted."""
+        k = ctypes.c_uint32(0)
+        with torch.cuda.device(self.device):
+            _check("ba_server_pump", lib().ba_server_pump(self._h, max_inflight, ctypes.addressof(k)))
+        return k.value
+
+    def poll(self, ticket: int):
+        """(state, done_ms, offset, bytes) of a ticket."""
+        st, ms, off, nb = ctypes.c_int(0), ctypes.c_double(0), ctypes.c_uint64(0), ctypes.c_uint64(0)
+        _check("ba_server_poll", lib().ba_server_poll(self._h, ticket, ctypes.addressof(st), ctypes.addressof(ms),
+                                                      ctypes.addressof(off), ctypes.addressof(nb)))
+        return st.value, ms.value, off.value, nb.value
+
+    def completed(self, capacity: int = 4096):
+        """Tickets that became ready or failed since the last call."""
+        buf = (ctypes.c_uint64 * capacity)()
+        k = ctypes.c_uint32(0)
+        _check("ba_server_completed", lib().ba_server_completed(self._h, ctypes.addressof(buf), capacity,
+                                                                ctypes.addressof(k)))
+        return [buf[i] for i in range(k.value)]
+
+    def result(self, ticket: int) -> torch.Tensor:
+        """A ready result as a view into the arena: int32[2m] edge pairs or
+        int64[first_k + 1] (degrees, then the checksum)."""
+        st, _, off, nb = self.poll(ticket)
+        if st != JOB_READY:
+            raise BAError("ba_server_poll", BA_EINVAL)
+        return self.arena[off:off + nb]
+
+    def release(self, ticket: int) -> None:
+        _check("ba_server_release", lib().ba_server_release(self._h, ticket))
+
+    def stats(self):
+        q, i, u = ctypes.c_uint64(0), ctypes.c_uint32(0), ctypes.c_uint64(0)
+        _check("ba_server_stats", lib().ba_server_stats(self._h, ctypes.addressof(q), ctypes.addressof(i),
+                                                        ctypes.addressof(u)))
+        return q.value, i.value, u.value

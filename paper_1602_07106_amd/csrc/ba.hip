@@ -34,6 +34,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <new>
 #include <utility>
 #include <vector>
 
@@ -703,6 +705,8 @@ static int current_device_slot(int *slot)
 
 }  // namespace ba
 
+#include "ba_server.h"
+
 using namespace ba;
 
 extern "C" {
@@ -1000,6 +1004,119 @@ int ba_batch_plan_rounds(uint32_t count, const uint64_t *n, const uint32_t *d, u
         off += need;
     }
     *rounds = count ? r + 1 : 0;
+    return BA_OK;
+}
+
+int ba_server_create(void *arena, uint64_t arena_bytes, void *stream, ba_server **out)
+{
+    if (!out || !arena || ((uintptr_t)arena & 255) || arena_bytes < 4096) return BA_EINVAL;
+    *out = nullptr;
+    ba_server *s = new (std::nothrow) ba_server();
+    if (!s) return BA_EINVAL;
+    s->arena = (unsigned char *)arena;
+    s->arena_bytes = arena_bytes & ~(uint64_t)255;
+    s->stream = (hipStream_t)stream;
+    s->alloc = ArenaAlloc(s->arena_bytes);
+    s->slot_bytes = batch_layout(kServerMaxBatch).bytes;
+    int rc = hip_check(hipHostMalloc((void **)&s->staging, s->slot_bytes * kServerSlots, hipHostMallocDefault));
+    if (!rc) rc = hip_check(hipEventCreate(&s->start));
+    if (!rc) rc = hip_check(hipEventRecord(s->start, s->stream));
+    if (rc) {
+        if (s->staging) (void)hipHostFree(s->staging);
+        if (s->start) (void)hipEventDestroy(s->start);
+        delete s;
+        return rc;
+    }
+    for (int k = kServerSlots - 1; k >= 0; k--) s->free_slots.push_back(k);
+    *out = s;
+    return BA_OK;
+}
+
+int ba_server_destroy(ba_server *s)
+{
+    if (!s) return BA_EINVAL;
+    int rc = hip_check(hipStreamSynchronize(s->stream));
+    for (auto &st : s->steps)
+        if (st.ev) (void)hipEventDestroy(st.ev);
+    if (s->start) (void)hipEventDestroy(s->start);
+    if (s->staging) (void)hipHostFree(s->staging);
+    delete s;
+    return rc;
+}
+
+int ba_server_submit(ba_server *s, const ba_request *r, uint64_t *ticket)
+{
+    if (!s || !r || !ticket) return BA_EINVAL;
+    uint64_t m;
+    if (!graph_fits(r->n, r->d, &m)) return BA_ERANGE;
+    if (r->kind == BA_REQ_EDGES) {
+        if (r->n > ((uint64_t)1 << 32)) return BA_ERANGE;
+    } else if (r->kind == BA_REQ_DEGREES) {
+        if (r->first_k > r->n) return BA_EINVAL;
+    } else {
+        return BA_EINVAL;
+    }
+    ServerJob J;
+    J.req = *r;
+    J.m = m;
+    J.out_bytes = job_output_bytes(*r, m);
+    *ticket = s->jobs.size();
+    s->jobs.push_back(J);
+    s->queue.push_back(*ticket);
+    return BA_OK;
+}
+
+int ba_server_pump(ba_server *s, uint32_t max_inflight, uint32_t *launched)
+{
+    if (!s || !launched) return BA_EINVAL;
+    *launched = 0;
+    int rc = server_retire(s);
+    if (rc) return rc;
+    if (s->queue.empty() || s->inflight >= max_inflight) return BA_OK;
+    return server_launch_step(s, launched);
+}
+
+int ba_server_poll(ba_server *s, uint64_t ticket, int *state, double *done_ms, uint64_t *offset, uint64_t *bytes)
+{
+    if (!s || ticket >= s->jobs.size() || !state) return BA_EINVAL;
+    int rc = server_retire(s);
+    if (rc) return rc;
+    const ServerJob &J = s->jobs[ticket];
+    *state = J.state;
+    if (done_ms) *done_ms = J.done_ms;
+    if (offset) *offset = J.out_off;
+    if (bytes) *bytes = J.out_bytes;
+    return BA_OK;
+}
+
+int ba_server_completed(ba_server *s, uint64_t *tickets, uint32_t capacity, uint32_t *count)
+{
+    if (!s || !count || (capacity && !tickets)) return BA_EINVAL;
+    int rc = server_retire(s);
+    if (rc) return rc;
+    const uint32_t k = (uint32_t)std::min<size_t>(capacity, s->completed.size());
+    for (uint32_t j = 0; j < k; j++) tickets[j] = s->completed[j];
+    s->completed.erase(s->completed.begin(), s->completed.begin() + k);
+    *count = k;
+    return BA_OK;
+}
+
+int ba_server_release(ba_server *s, uint64_t ticket)
+{
+    if (!s || ticket >= s->jobs.size()) return BA_EINVAL;
+    ServerJob &J = s->jobs[ticket];
+    if (J.state != BA_JOB_READY) return BA_EINVAL;
+    s->alloc.release(J.out_off, J.out_bytes);
+    J.state = BA_JOB_RELEASED;
+    return BA_OK;
+}
+
+int ba_server_stats(ba_server *s, uint64_t *queued, uint32_t *inflight, uint64_t *arena_used)
+{
+    if (!s) return BA_EINVAL;
+    if (queued) *queued = s->queue.size();
+    if (inflight) *inflight = s->inflight;
+    if (arena_used) *arena_used = s->alloc.used();
     return BA_OK;
 }
 

@@ -24,3 +24,22 @@ def test_batch_instances_distribution():
     assert abs(n.mean() / 1.0856e6 - 1) < 0.15 and abs(d.mean() - 16.5) < 0.6
     logn = np.log10(n.astype(np.float64))
     assert abs(np.mean(logn) - 5.0) < 0.05
+
+
+def test_served_trace_shape():
+    t = workloads.served_trace()
+    n, d, kind = t["n"], t["d"], t["kind"]
+    assert len(n) == 4000 and np.all(np.diff(t["arrival_s"]) > 0)
+    rate = len(n) / t["arrival_s"][-1]
+    assert 1800 < rate < 2200  # Poisson arrivals at 2000/s
+    big = (n == (1 << 27)) & (d == 16)
+    assert 0.01 < big.mean() < 0.03
+    assert set(np.unique(d).tolist()) <= {2, 4, 8, 16, 32, 64}
+    assert n.min() >= 10**4 and n[~big].max() <= 10**8
+    assert 0.45 < kind.mean() < 0.55
+    assert np.all(t["first_k"][kind == 1] == np.minimum(n[kind == 1], 100000))
+    assert np.all(t["first_k"][kind == 0] == 0)
+    assert t["seed"].tolist() == list(range(4000))
+    # offered load: mean edges per request x rate, about 5e11 edges/s
+    offered = float((n.astype(np.float64) * d).mean()) * rate
+    assert 3e11 < offered < 8e11

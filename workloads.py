@@ -27,3 +27,30 @@ def batch_instances(count: int = 4096, seed: int = BATCH_SEED):
     d = (1 + rng.integers(0, 32, size=count)).astype(np.uint32)
     s = np.arange(count, dtype=np.uint64)
     return n, d, s
+
+
+SERVED_SEED = 0x5E4FED
+
+
+def served_trace(count: int = 4000, rate: float = 2000.0, seed: int = SERVED_SEED, n_lo: float = 1e4,
+                 n_hi: float = 1e8, big_frac: float = 0.02):
+    """The served workload: `count` requests with Poisson arrivals at `rate`
+    per second.  A fraction big_frac asks for the n=2^27, d=16 graph; the
+    rest have n log-uniform on [n_lo, n_hi] and d uniform on {2,4,...,64}.
+    Half the requests want the whole edge list, half the streamed degrees
+    of the first min(10^5, n) nodes.  The hash seed of request j is j.
+    Returns a dict of numpy arrays: arrival_s, n, d, seed, kind (0 edges,
+    1 degrees), first_k."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    arrival = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    u = rng.random(count)
+    n = np.clip(np.rint(10.0 ** (np.log10(n_lo) + (np.log10(n_hi) - np.log10(n_lo)) * u)), n_lo, n_hi)
+    n = n.astype(np.uint64)
+    d = (2 ** rng.integers(1, 7, size=count)).astype(np.uint32)
+    big = rng.random(count) < big_frac
+    n[big] = 1 << 27
+    d[big] = 16
+    kind = (rng.random(count) < 0.5).astype(np.uint32)
+    first_k = np.where(kind == 1, np.minimum(n, 100000), 0).astype(np.uint64)
+    return {"arrival_s": arrival, "n": n, "d": d, "seed": np.arange(count, dtype=np.uint64), "kind": kind,
+            "first_k": first_k}
