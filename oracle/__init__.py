@@ -22,6 +22,11 @@ Functions follow the paper section by section:
   first k nodes) plus the edge checksum.
 * ``count_degrees`` / ``checksum_E`` -- occurrence counts and the checksum of
   a stored edge array.
+* ``model_*`` (``bb_model.c``) -- the generalizations of Section
+  "Generalizations": a seed graph of n0 nodes and m0 edges in front of the
+  edge array, and draws that avoid self-loops; ``crc32c_*`` / ``h_crc`` --
+  the paper's CRC-based hash (figure with hash_crc) as an alternative
+  keyed hash.
 """
 from __future__ import annotations
 
@@ -33,6 +38,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bb_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "bb_model.c")]
 _LIB = os.path.join(_HERE, "libbb_oracle.so")
 
 _u64 = ctypes.c_uint64
@@ -40,11 +46,12 @@ _p = ctypes.c_void_p
 
 
 def build(force: bool = False) -> str:
-    """Compile bb_oracle.c into libbb_oracle.so with gcc (plain -O2)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile bb_oracle.c and bb_model.c into libbb_oracle.so with gcc (plain -O2)."""
+    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS)
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", tmp, _SRC]
+            ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", tmp] + _SRCS
         )
         os.replace(tmp, _LIB)
     return _LIB
@@ -71,6 +78,14 @@ def lib() -> ctypes.CDLL:
             ("bbo_edge", None, [_u64, _u64, _u64, _p, _p, _p]),
             ("bbo_edges_range", None, [_u64, _u64, _u64, _u64, _p, _p]),
             ("bbo_stream", None, [_u64, _u64, _u64, _u64, _u64, _p, _p, _p]),
+            ("bbo_crc32c_update", ctypes.c_uint32, [ctypes.c_uint32, _p, _u64]),
+            ("bbo_crc32c_u64", ctypes.c_uint32, [ctypes.c_uint32, _u64]),
+            ("bbo_h_crc", _u64, [_u64, _u64, _u64]),
+            ("bbo_h_fmix", _u64, [_u64, _u64, _u64]),
+            ("bbo_model_bb_generate", ctypes.c_int, [_u64, _u64, _p, _u64, _u64, _u64, ctypes.c_uint, _p, _p]),
+            ("bbo_model_bb_with_choices", ctypes.c_int, [_u64, _u64, _p, _u64, _u64, ctypes.c_uint, _p, _p]),
+            ("bbo_model_edge", None, [_u64, _u64, _p, _u64, _u64, ctypes.c_uint, _p, _u64, _p, _p, _p]),
+            ("bbo_model_edges_range", None, [_u64, _u64, _p, _u64, _u64, ctypes.c_uint, _u64, _u64, _p, _p]),
         ]:
             f = getattr(L, name)
             f.restype = res
@@ -167,3 +182,73 @@ def stream(d: int, seed: int, i0: int, count: int, k: int, deg_k=None, cs: int =
     calls = _u64(0)
     lib().bbo_stream(d, seed, i0, count, k, _ptr(deg_k), ctypes.addressof(c), ctypes.addressof(calls))
     return deg_k, c.value, calls.value
+
+
+NO_LOOPS, CRC = 1, 2
+
+
+def crc32c_update(crc: int, data: bytes) -> int:
+    buf = np.frombuffer(bytes(data), dtype=np.uint8)
+    return int(lib().bbo_crc32c_update(crc, buf.ctypes.data if buf.size else None, buf.size))
+
+
+def crc32c_u64(crc: int, x: int) -> int:
+    return int(lib().bbo_crc32c_u64(crc, x))
+
+
+def h_crc(key_: int, r: int, bound: int) -> int:
+    return int(lib().bbo_h_crc(key_, r, bound))
+
+
+def h_fmix(key_: int, r: int, bound: int) -> int:
+    return int(lib().bbo_h_fmix(key_, r, bound))
+
+
+def _seed_arr(S, m0):
+    S = np.ascontiguousarray(np.asarray(S if S is not None else [], dtype=np.uint32))
+    assert S.size == 2 * m0
+    return S
+
+
+def model_bb_generate(n0: int, m0: int, S, n: int, d: int, seed: int, flags: int = 0) -> np.ndarray:
+    """Batagelj-Brandes with a seed graph: all 2*m0 + 2*(n-n0)*d positions."""
+    S = _seed_arr(S, m0)
+    E = np.empty(2 * m0 + 2 * (n - n0) * d, dtype=np.uint32)
+    calls = _u64(0)
+    rc = lib().bbo_model_bb_generate(n0, m0, S.ctypes.data if S.size else None, n, d, seed, flags,
+                                     E.ctypes.data if E.size else None, ctypes.addressof(calls))
+    if rc != 0:
+        raise ValueError("model_bb_generate: rc %d" % rc)
+    return E
+
+
+def model_bb_with_choices(n0: int, m0: int, S, n: int, d: int, flags: int, x) -> np.ndarray:
+    S = _seed_arr(S, m0)
+    xs = np.ascontiguousarray(np.asarray(x, dtype=np.uint64))
+    E = np.empty(2 * m0 + 2 * (n - n0) * d, dtype=np.uint32)
+    rc = lib().bbo_model_bb_with_choices(n0, m0, S.ctypes.data if S.size else None, n, d, flags,
+                                         xs.ctypes.data if xs.size else None, E.ctypes.data if E.size else None)
+    if rc != 0:
+        raise ValueError("model_bb_with_choices: rc %d" % rc)
+    return E
+
+
+def model_edge(n0: int, m0: int, S, d: int, seed: int, flags: int, i: int, x=None):
+    """(u, v, draws) of new edge i; with x given, the draws come from it."""
+    S = _seed_arr(S, m0)
+    xs = None if x is None else np.ascontiguousarray(np.asarray(x, dtype=np.uint64))
+    u, v, s = _u64(0), _u64(0), _u64(0)
+    lib().bbo_model_edge(n0, m0, S.ctypes.data if S.size else None, d, seed, flags,
+                         None if xs is None else xs.ctypes.data, i, ctypes.addressof(u), ctypes.addressof(v),
+                         ctypes.addressof(s))
+    return u.value, v.value, s.value
+
+
+def model_edges_range(n0: int, m0: int, S, d: int, seed: int, flags: int, i0: int, count: int):
+    """(uint32[count, 2] new edges i0.., total draws)."""
+    S = _seed_arr(S, m0)
+    out = np.empty((count, 2), dtype=np.uint32)
+    steps = _u64(0)
+    lib().bbo_model_edges_range(n0, m0, S.ctypes.data if S.size else None, d, seed, flags, i0, count,
+                                out.ctypes.data if count else None, ctypes.addressof(steps))
+    return out, steps.value
