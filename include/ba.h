@@ -273,6 +273,36 @@ int ba_server_completed(ba_server *s, uint64_t *tickets, uint32_t capacity, uint
 int ba_server_release(ba_server *s, uint64_t ticket);
 int ba_server_stats(ba_server *s, uint64_t *queued, uint32_t *inflight, uint64_t *arena_used);
 
+/*
+ * The generalized model (paper Section "Generalizations") and the paper's
+ * CRC-based hash.  A seed graph of n0 nodes (IDs 0..n0-1) and m0 edges
+ * (seed_edges: device array of 2*m0 node IDs below n0, pairs) occupies the
+ * first 2*m0 positions of the edge array; nodes n0..n-1 then join with d
+ * edges each.  New edge i (0 <= i < (n-n0)*d) is (n0 + floor(i/d), v_i),
+ * where v_i follows positions r = 2*m0 + 2i + 1, x(r), x(x(r)), ... until a
+ * seed position (v = seed_edges[r]) or an even position 2*m0 + 2j
+ * (v = n0 + floor(j/d)).  The draw x(r) lies below
+ *   r                               (default: self-loops allowed), or
+ *   2*m0 + 2*d*floor(i/d)           (BA_NO_SELF_LOOPS: positions before the
+ *                                    new node's own first edge, so v != u),
+ * and is a hash of r itself: umul64hi(fmix64(r ^ key), bound) by default,
+ * or with BA_HASH_CRC ((crc32c(0,z) << 32) + crc32c(1,z)) mod bound with
+ * z = r ^ key (crc32c: the CRC-32C register update over the 8 bytes of z,
+ * as the SSE4.2 crc32 instruction; with seed 0 this is the paper's
+ * hash_crc).  With n0 = m0 = 0, no flags, it is ba_generate's graph.
+ *
+ * ba_generate_model writes new edges edge_begin .. edge_begin+edge_count-1
+ * as uint32 pairs to `edges` (device, 2*edge_count, 4-byte aligned).
+ * BA_EINVAL: unknown flags, n0 > n, null/misaligned buffers, a range past
+ * (n-n0)*d, or BA_NO_SELF_LOOPS with m0 = 0 (node n0 would have nothing to
+ * attach to); BA_ERANGE: n > 2^32 or positions beyond 2^63.  The seed
+ * graph's IDs are not checked; IDs >= n0 pass through to the output.
+ */
+enum { BA_NO_SELF_LOOPS = 1, BA_HASH_CRC = 2 };
+int ba_generate_model(uint64_t n, uint32_t d, uint64_t seed, uint64_t n0, uint64_t m0,
+                      const uint32_t *seed_edges, uint32_t flags, uint64_t edge_begin,
+                      uint64_t edge_count, uint32_t *edges, void *stream);
+
 /* Text for a status code (static storage, never NULL). */
 const char *ba_strerror(int status);
 

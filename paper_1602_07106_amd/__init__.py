@@ -44,6 +44,7 @@ __all__ = [
     "batch_shape",
     "generate_batch",
     "Server",
+    "generate_model",
     "lib",
     "library_path",
 ]
@@ -86,6 +87,7 @@ _SIGS = {
     "ba_batch_current_shape": (_int, [_p]),
     "ba_batch_shape_dims": (_int, [_int, _p, _p]),
     "ba_batch_plan_rounds": (_int, [_u32, _p, _p, _u64, _p, _p, _p]),
+    "ba_generate_model": (_int, [_u64, _u32, _u64, _u64, _u64, _p, _u32, _u64, _u64, _p, _p]),
     "ba_server_create": (_int, [_p, _u64, _p, _p]),
     "ba_server_destroy": (_int, [_p]),
     "ba_server_submit": (_int, [_p, _p, _p]),
@@ -513,3 +515,37 @@ class Server:
         _check("ba_server_stats", lib().ba_server_stats(self._h, ctypes.addressof(q), ctypes.addressof(i),
                                                         ctypes.addressof(u)))
         return q.value, i.value, u.value
+
+
+NO_SELF_LOOPS, HASH_CRC = 1, 2
+
+
+def generate_model(n: int, d: int, seed: int, *, n0: int = 0, seed_edges: Optional[torch.Tensor] = None,
+                   no_self_loops: bool = False, hash: str = "fmix", begin: int = 0, count: Optional[int] = None,
+                   out: Optional[torch.Tensor] = None, device=None) -> torch.Tensor:
+    """New edges begin..begin+count-1 of the generalized model (see
+    ba_generate_model) as int32[count, 2]: a seed graph of n0 nodes whose
+    edges are the int32 device tensor seed_edges (2*m0 IDs), optional
+    self-loop-free draws, and the fmix or the paper's crc hash."""
+    if hash not in ("fmix", "crc"):
+        raise ValueError("hash must be 'fmix' or 'crc'")
+    m0 = 0
+    sp = None
+    if seed_edges is not None:
+        if seed_edges.dtype != torch.int32 or seed_edges.numel() % 2:
+            raise ValueError("seed_edges must be int32 with 2*m0 elements")
+        m0 = seed_edges.numel() // 2
+        sp = _ptr(seed_edges)
+        device = seed_edges.device if device is None else device
+    if count is None:
+        count = (n - n0) * d - begin
+    dev = _device(device if out is None else out.device)
+    if out is None:
+        out = torch.empty((count, 2), dtype=torch.int32, device=dev)
+    elif out.dtype != torch.int32 or out.numel() != 2 * count:
+        raise ValueError("out must be int32 with 2*count elements")
+    flags = (NO_SELF_LOOPS if no_self_loops else 0) | (HASH_CRC if hash == "crc" else 0)
+    with torch.cuda.device(dev):
+        _check("ba_generate_model", lib().ba_generate_model(n, d, seed, n0, m0, sp, flags, begin, count,
+                                                            _ptr(out) if count else None, _stream(dev)))
+    return out

@@ -111,12 +111,14 @@ __device__ __forceinline__ void store_pair(uint32_t *out, uint32_t j, uint32_t t
 // The chain loop of one tile of tn edges (paper Section 2, figure
 // generateEdge): lane-refill over the tile.  rbase = 2*(first edge)+1, so
 // edge li of the tile starts at position rbase + 2*li.  A lane whose chain
-// reaches an even position stores out(r) at stage[li] and takes the next
-// unclaimed edge.  While a whole wave's worth of edges is unclaimed every
-// lane is busy and no per-lane bounds test is needed; the tail then runs
-// the last chains with finished lanes idle.
-template <class R, class H, class O>
-__device__ __forceinline__ void chain_tile(uint32_t *stage, uint32_t tn, uint32_t lane, R rbase, H hash, O out)
+// reaches a final position (stop(r): an even position, or a seed-graph
+// position in the generalized model) stores out(r) at stage[li] and takes
+// the next unclaimed edge.  While a whole wave's worth of edges is
+// unclaimed every lane is busy and no per-lane bounds test is needed; the
+// tail then runs the last chains with finished lanes idle.
+template <class R, class H, class S, class O>
+__device__ __forceinline__ void chain_tile_until(uint32_t *stage, uint32_t tn, uint32_t lane, R rbase, H hash,
+                                                 S stop, O out)
 {
     tn = __builtin_amdgcn_readfirstlane(tn);  // wave-uniform: keeps loop control scalar
     uint32_t li = lane;
@@ -125,8 +127,9 @@ __device__ __forceinline__ void chain_tile(uint32_t *stage, uint32_t tn, uint32_
     if (tn >= kWave) {
         while (next + kWave <= tn) {
             r = hash(r);
-            const uint64_t dm = __ballot(!(r & 1));
-            if (!(r & 1)) {
+            const bool fin = stop(r);
+            const uint64_t dm = __ballot(fin);
+            if (fin) {
                 stage[li] = out(r);
                 li = next + lane_rank(dm);
                 r = rbase + 2 * (R)li;
@@ -139,7 +142,7 @@ __device__ __forceinline__ void chain_tile(uint32_t *stage, uint32_t tn, uint32_
     uint64_t live = __ballot(active);
     while (live) {
         r = hash(r);
-        const bool done = active && !(r & 1);
+        const bool done = active && stop(r);
         const uint64_t dm = __ballot(done);
         if (done) {
             stage[li] = out(r);
@@ -150,6 +153,13 @@ __device__ __forceinline__ void chain_tile(uint32_t *stage, uint32_t tn, uint32_
         next += (uint32_t)__popcll(dm);
         live = __ballot(active);
     }
+}
+
+// The plain model: chains end at the first even position.
+template <class R, class H, class O>
+__device__ __forceinline__ void chain_tile(uint32_t *stage, uint32_t tn, uint32_t lane, R rbase, H hash, O out)
+{
+    chain_tile_until(stage, tn, lane, rbase, hash, [](R r) { return !(r & 1); }, out);
 }
 
 // One chain step for every lane, then refill of the lanes that finished.
@@ -201,6 +211,7 @@ __global__ __launch_bounds__(kGenBlock) void k_gen_u32(GenArgs a)
 }  // namespace ba
 
 #include "ba_batch.h"
+#include "ba_model.h"
 
 namespace ba {
 
@@ -703,6 +714,23 @@ static int current_device_slot(int *slot)
     return BA_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Generalized model (seed graph, self-loop-free draws, CRC hash).
+
+static constexpr CrcTables kHostCrcTables = make_crc_tables();
+
+template <bool C, bool L>
+static int launch_model_one(const ModelArgs &a, hipStream_t st)
+{
+    uint32_t grid = 0;
+    int rc = persistent_grid(k_gen_model<C, L>, kGenBlock, &grid);
+    if (rc) return rc;
+    grid = grid_for(a.ntiles, kGenWaves, grid);
+    return launch_timed(BA_KT_GEN, st,
+                        [&] { hipLaunchKernelGGL((k_gen_model<C, L>), dim3(grid), dim3(kGenBlock), 0, st, a); });
+}
+
 }  // namespace ba
 
 #include "ba_server.h"
@@ -1118,6 +1146,39 @@ int ba_server_stats(ba_server *s, uint64_t *queued, uint32_t *inflight, uint64_t
     if (inflight) *inflight = s->inflight;
     if (arena_used) *arena_used = s->alloc.used();
     return BA_OK;
+}
+
+int ba_generate_model(uint64_t n, uint32_t d, uint64_t seed, uint64_t n0, uint64_t m0, const uint32_t *seed_edges,
+                      uint32_t flags, uint64_t edge_begin, uint64_t edge_count, uint32_t *edges, void *stream)
+{
+    if (flags & ~(uint32_t)(BA_NO_SELF_LOOPS | BA_HASH_CRC)) return BA_EINVAL;
+    if (n0 > n) return BA_EINVAL;
+    if (n > ((uint64_t)1 << 32)) return BA_ERANGE;
+    uint64_t m;
+    if (!graph_fits(n - n0, d, &m)) return BA_ERANGE;
+    const unsigned __int128 pos = (unsigned __int128)2 * m0 + (unsigned __int128)2 * m;
+    if (pos >> 63) return BA_ERANGE;
+    if ((m0 && !seed_edges) || ((uintptr_t)seed_edges & 3)) return BA_EINVAL;
+    if ((flags & BA_NO_SELF_LOOPS) && m0 == 0 && m > 0) return BA_EINVAL;
+    if (edge_begin > m || edge_count > m - edge_begin) return BA_EINVAL;
+    if ((edge_count && !edges) || ((uintptr_t)edges & 3)) return BA_EINVAL;
+    if (edge_count == 0) return BA_OK;
+    ModelArgs a{};
+    a.key = make_hash_key(seed);
+    a.key64 = seed * kPhi64;
+    a.k1 = crc32c_u64(kHostCrcTables.t, 1u, 0);
+    a.div = make_divider(d);
+    a.P0 = 2 * m0;
+    a.n0 = n0;
+    a.S = seed_edges;
+    a.begin = edge_begin;
+    a.count = edge_count;
+    a.ntiles = (edge_count + kTile - 1) / kTile;
+    a.edges = edges;
+    hipStream_t st = (hipStream_t)stream;
+    const bool crc = flags & BA_HASH_CRC, noloops = flags & BA_NO_SELF_LOOPS;
+    if (crc) return noloops ? launch_model_one<true, true>(a, st) : launch_model_one<true, false>(a, st);
+    return noloops ? launch_model_one<false, true>(a, st) : launch_model_one<false, false>(a, st);
 }
 
 const char *ba_strerror(int status)

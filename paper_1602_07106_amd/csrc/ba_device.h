@@ -84,19 +84,23 @@ __device__ __forceinline__ uint32_t hash_narrow(uint32_t r, const HashKey &k)
     return (uint32_t)(mad64(hi, r, t) >> 32);
 }
 
-// h(r) for any 64-bit r >= 1.
-__device__ __forceinline__ uint64_t hash_wide(uint64_t r, const HashKey &k)
+// umul64hi(fmix64(r XOR key), b) for any 64-bit r and b >= 1: a value in
+// 0..b-1 (the draw bound b is r itself in the plain model).
+__device__ __forceinline__ uint64_t hash_bounded(uint64_t r, uint64_t b, const HashKey &k)
 {
-    uint32_t r0 = (uint32_t)r, r1 = (uint32_t)(r >> 32);
-    uint32_t lo = r0 ^ k.klo, hi = r1 ^ k.khi;
+    uint32_t lo = (uint32_t)r ^ k.klo, hi = (uint32_t)(r >> 32) ^ k.khi;
     lo ^= shr64_lo(hi, lo, 30);
     hi ^= hi >> 30;
     fmix_tail(lo, hi, hi * kC1Lo);
-    // umul64hi((hi:lo), (r1:r0))
-    uint64_t t = mad64(lo, r1, __umulhi(lo, r0));
-    uint64_t u = mad64(hi, r0, (uint32_t)t);
-    return mad64(hi, r1, (t >> 32) + (u >> 32));
+    // umul64hi((hi:lo), (b1:b0))
+    const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    uint64_t t = mad64(lo, b1, __umulhi(lo, b0));
+    uint64_t u = mad64(hi, b0, (uint32_t)t);
+    return mad64(hi, b1, (t >> 32) + (u >> 32));
 }
+
+// h(r) for any 64-bit r >= 1.
+__device__ __forceinline__ uint64_t hash_wide(uint64_t r, const HashKey &k) { return hash_bounded(r, r, k); }
 
 // Exact floor(x / d) for a fixed d >= 1 (Granlund & Montgomery, "Division by
 // invariant integers using multiplication", PLDI 1994, the round-up method

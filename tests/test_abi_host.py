@@ -174,3 +174,15 @@ def test_batch_host_validation_without_gpu():
     assert L.ba_batch_launch_shape(ctypes.addressof(info), None, None, 0, 5, None) == ba.BA_EINVAL
     assert [ba.batch_shape(k)[1:] for k in range(ba.BATCH_SHAPES)] == [(2048, 4), (1024, 4), (4096, 4), (1024, 8),
                                                                        (2048, 8)]
+
+
+def test_model_argument_checks_without_gpu():
+    L = ba.lib()
+    # unknown flag, n0 > n, no-self-loops without a seed edge, range past the new edges
+    assert L.ba_generate_model(100, 2, 1, 0, 0, None, 4, 0, 1, 16, None) == ba.BA_EINVAL
+    assert L.ba_generate_model(100, 2, 1, 101, 0, None, 0, 0, 0, None, None) == ba.BA_EINVAL
+    assert L.ba_generate_model(100, 2, 1, 0, 0, None, ba.NO_SELF_LOOPS, 0, 1, 16, None) == ba.BA_EINVAL
+    assert L.ba_generate_model(100, 2, 1, 10, 0, None, 0, 180, 1, 16, None) == ba.BA_EINVAL
+    assert L.ba_generate_model(100, 2, 1, 10, 3, None, 0, 0, 1, 16, None) == ba.BA_EINVAL  # seed edges missing
+    assert L.ba_generate_model((1 << 32) + 1, 1, 1, 0, 0, None, 0, 0, 0, None, None) == ba.BA_ERANGE
+    assert L.ba_generate_model(100, 2, 1, 10, 0, None, 0, 5, 0, None, None) == ba.BA_OK  # empty range

@@ -1,0 +1,96 @@
+"""GPU parity of the generalized model (seed graph, self-loop-free draws,
+the paper's CRC hash) against the CPU oracle, bit-exact: every flag
+combination, seed graphs of several shapes, ranges at odd offsets,
+misaligned outputs, and 64-bit positions."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1602_07106_amd as ba  # noqa: E402
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ba.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+FLAGS = [(False, "fmix"), (True, "fmix"), (False, "crc"), (True, "crc")]
+
+
+def _oflags(no_loops, h):
+    return (oracle.NO_LOOPS if no_loops else 0) | (oracle.CRC if h == "crc" else 0)
+
+
+def _seed_graph(n0, m0, seed):
+    S = np.random.default_rng(seed).integers(0, max(n0, 1), 2 * m0).astype(np.uint32)
+    return S, torch.from_numpy(S.view(np.int32).copy()).to("cuda")
+
+
+@pytest.mark.parametrize("no_loops,h", FLAGS)
+@pytest.mark.parametrize("n0,m0,n,d,seed", [(1, 1, 3000, 3, 5), (40, 70, 20000, 7, 6), (500, 2000, 9000, 1, 7),
+                                             (3, 2, 5000, 16, 0)])
+def test_model_matches_the_oracle(no_loops, h, n0, m0, n, d, seed):
+    _say("model", no_loops, h, n0, m0, n, d, seed)
+    S, St = _seed_graph(n0, m0, seed + 100)
+    m = (n - n0) * d
+    out = ba.generate_model(n, d, seed, n0=n0, seed_edges=St, no_self_loops=no_loops, hash=h)
+    torch.cuda.synchronize()
+    ref, _ = oracle.model_edges_range(n0, m0, S, d, seed, _oflags(no_loops, h), 0, m)
+    got = out.cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, ref)
+    if no_loops:
+        assert np.all(got[:, 1] != got[:, 0])
+
+
+@pytest.mark.parametrize("no_loops,h", FLAGS)
+def test_model_ranges_and_misaligned_outputs(no_loops, h):
+    n0, m0, n, d, seed = 30, 45, 40000, 5, 11
+    S, St = _seed_graph(n0, m0, 3)
+    m = (n - n0) * d
+    for b, c in [(1, 7777), (m - 3001, 3001), (12345, 1)]:
+        _say("model range", no_loops, h, b, c)
+        buf = torch.full((2 * c + 1,), -1, dtype=torch.int32, device="cuda")
+        out = buf[1:].view(c, 2)  # 4-byte aligned only
+        ba.generate_model(n, d, seed, n0=n0, seed_edges=St, no_self_loops=no_loops, hash=h, begin=b, count=c,
+                          out=out)
+        torch.cuda.synchronize()
+        ref, _ = oracle.model_edges_range(n0, m0, S, d, seed, _oflags(no_loops, h), b, c)
+        assert np.array_equal(out.cpu().numpy().view(np.uint32), ref)
+        assert int(buf[0]) == -1
+
+
+def test_trivial_seed_graph_is_the_plain_generator():
+    n, d, seed = 50000, 6, 21
+    a = ba.generate_model(n, d, seed)
+    b, _ = ba.generate(n, d, seed)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("no_loops,h", FLAGS)
+def test_model_with_64_bit_positions(no_loops, h):
+    n0, m0, d, seed = 7, 1000, 17, 4
+    n = (1 << 28) + 5  # positions beyond 2^32
+    S, St = _seed_graph(n0, m0, 9)
+    m = (n - n0) * d
+    for b in [0, (1 << 31) - 500, m - 1000]:
+        _say("model wide", no_loops, h, b)
+        out = ba.generate_model(n, d, seed, n0=n0, seed_edges=St, no_self_loops=no_loops, hash=h, begin=b, count=1000)
+        torch.cuda.synchronize()
+        ref, _ = oracle.model_edges_range(n0, m0, S, d, seed, _oflags(no_loops, h), b, 1000)
+        assert np.array_equal(out.cpu().numpy().view(np.uint32), ref)
