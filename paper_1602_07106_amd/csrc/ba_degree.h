@@ -433,8 +433,7 @@ __global__ __launch_bounds__(kHBlock) void k_deg_hist(DegArgs a)
         if (lane < head) atomicAdd(&cnt[src[lane]], 1u);
         const uint32_t nv = (n - head) / 8;
         const uint4 *vs = reinterpret_cast<const uint4 *>(src + head);
-        for (uint32_t t = lane; t < nv; t += 64) {
-            const uint4 q = vs[t];
+        auto count8 = [&](const uint4 &q) {
             atomicAdd(&cnt[q.x & 0xFFFFu], 1u);
             atomicAdd(&cnt[q.x >> 16], 1u);
             atomicAdd(&cnt[q.y & 0xFFFFu], 1u);
@@ -443,19 +442,40 @@ __global__ __launch_bounds__(kHBlock) void k_deg_hist(DegArgs a)
             atomicAdd(&cnt[q.z >> 16], 1u);
             atomicAdd(&cnt[q.w & 0xFFFFu], 1u);
             atomicAdd(&cnt[q.w >> 16], 1u);
+        };
+        // four 16-byte loads in flight per lane before their 32 atomics
+        uint32_t t = lane;
+        for (; t + 192 < nv; t += 256) {
+            const uint4 q0 = vs[t], q1 = vs[t + 64], q2 = vs[t + 128], q3 = vs[t + 192];
+            count8(q0);
+            count8(q1);
+            count8(q2);
+            count8(q3);
         }
+        for (; t < nv; t += 64) count8(vs[t]);
         for (uint32_t x = head + nv * 8 + lane; x < n; x += 64) atomicAdd(&cnt[src[x]], 1u);
     }
     __syncthreads();
     const uint64_t vbase = (uint64_t)g << kS2;
-    for (uint32_t y = threadIdx.x; y < kSub; y += kHBlock) {
-        const uint64_t v = vbase + y;
-        const uint32_t c = cnt[y];
-        if (c && v < a.p.n) {
-            if (np == 1)
-                a.deg[v] += c;
-            else
-                deg_atomic_add(a.deg, v, c);
+    static_assert(kSub % (8 * kHBlock) == 0, "count write-back batches");
+    for (uint32_t y0 = threadIdx.x; y0 < kSub; y0 += 8 * kHBlock) {
+        uint32_t c[8];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; u++) {
+            const uint64_t v = vbase + y0 + u * kHBlock;
+            c[u] = v < a.p.n ? cnt[y0 + u * kHBlock] : 0u;
+        }
+        if (np == 1) {  // the only block of this sub-bucket: plain read-modify-write, 8 reads in flight
+            uint32_t old[8];
+#pragma unroll
+            for (uint32_t u = 0; u < 8; u++) old[u] = c[u] ? a.deg[vbase + y0 + u * kHBlock] : 0u;
+#pragma unroll
+            for (uint32_t u = 0; u < 8; u++)
+                if (c[u]) a.deg[vbase + y0 + u * kHBlock] = old[u] + c[u];
+        } else {
+#pragma unroll
+            for (uint32_t u = 0; u < 8; u++)
+                if (c[u]) deg_atomic_add(a.deg, vbase + y0 + u * kHBlock, c[u]);
         }
     }
 }
