@@ -248,7 +248,9 @@ int ba_batch_plan_rounds(uint32_t count, const uint64_t *n, const uint32_t *d, u
  * offset/size of its result in the arena.  ba_server_completed hands out
  * (up to capacity) the tickets that became ready or failed since its last
  * call, oldest first, so a client need not poll every ticket.
- * ba_server_release returns a ready result's arena space.  ba_server_destroy waits for the stream and
+ * ba_server_release returns a ready result's arena space (or drops a
+ * failed request); a ticket is valid until it is released, and the
+ * server's host memory follows the tickets still held.  ba_server_destroy waits for the stream and
  * frees the server (not the arena).  One host thread per server; calls on
  * one server must not overlap.
  */

@@ -1064,8 +1064,7 @@ int ba_server_destroy(ba_server *s)
 {
     if (!s) return BA_EINVAL;
     int rc = hip_check(hipStreamSynchronize(s->stream));
-    for (auto &st : s->steps)
-        if (st.ev) (void)hipEventDestroy(st.ev);
+    for (auto &st : s->steps) (void)hipEventDestroy(st.ev);
     if (s->start) (void)hipEventDestroy(s->start);
     if (s->staging) (void)hipHostFree(s->staging);
     delete s;
@@ -1088,7 +1087,7 @@ int ba_server_submit(ba_server *s, const ba_request *r, uint64_t *ticket)
     J.req = *r;
     J.m = m;
     J.out_bytes = job_output_bytes(*r, m);
-    *ticket = s->jobs.size();
+    *ticket = s->job_base + s->jobs.size();
     s->jobs.push_back(J);
     s->queue.push_back(*ticket);
     return BA_OK;
@@ -1106,10 +1105,12 @@ int ba_server_pump(ba_server *s, uint32_t max_inflight, uint32_t *launched)
 
 int ba_server_poll(ba_server *s, uint64_t ticket, int *state, double *done_ms, uint64_t *offset, uint64_t *bytes)
 {
-    if (!s || ticket >= s->jobs.size() || !state) return BA_EINVAL;
+    if (!s || !state) return BA_EINVAL;
     int rc = server_retire(s);
     if (rc) return rc;
-    const ServerJob &J = s->jobs[ticket];
+    const ServerJob *Jp = server_job(s, ticket);
+    if (!Jp) return BA_EINVAL;
+    const ServerJob &J = *Jp;
     *state = J.state;
     if (done_ms) *done_ms = J.done_ms;
     if (offset) *offset = J.out_off;
@@ -1131,11 +1132,12 @@ int ba_server_completed(ba_server *s, uint64_t *tickets, uint32_t capacity, uint
 
 int ba_server_release(ba_server *s, uint64_t ticket)
 {
-    if (!s || ticket >= s->jobs.size()) return BA_EINVAL;
-    ServerJob &J = s->jobs[ticket];
-    if (J.state != BA_JOB_READY) return BA_EINVAL;
-    s->alloc.release(J.out_off, J.out_bytes);
-    J.state = BA_JOB_RELEASED;
+    if (!s) return BA_EINVAL;
+    ServerJob *J = server_job(s, ticket);
+    if (!J || (J->state != BA_JOB_READY && J->state != BA_JOB_FAILED)) return BA_EINVAL;
+    if (J->state == BA_JOB_READY) s->alloc.release(J->out_off, J->out_bytes);
+    J->state = BA_JOB_RELEASED;
+    server_trim(s);
     return BA_OK;
 }
 

@@ -71,7 +71,6 @@ struct ServerJob {
     uint64_t m = 0;
     uint64_t out_off = 0, out_bytes = 0;
     int state = BA_JOB_QUEUED;
-    int64_t step = -1;
     double done_ms = 0.0;
 };
 
@@ -80,7 +79,6 @@ struct ServerStep {
     uint64_t table_off = 0, table_bytes = 0;
     int slot = -1;  // pinned staging slot holding the table, returned when the step retires
     std::vector<uint64_t> jobs;
-    bool done = false;
 };
 
 constexpr uint32_t kServerSlots = 8;         // steps in flight at most
@@ -94,11 +92,13 @@ struct ba_server {
     hipStream_t stream = nullptr;
     hipEvent_t start = nullptr;
     ba::ArenaAlloc alloc{0};
-    std::vector<ba::ServerJob> jobs;
+    // jobs of tickets job_base .. job_base + jobs.size() - 1; released jobs
+    // leave from the front, so memory follows the jobs still held
+    std::deque<ba::ServerJob> jobs;
+    uint64_t job_base = 0;
     std::deque<uint64_t> queue;
-    std::vector<ba::ServerStep> steps;
-    size_t first_live = 0;  // steps before it have retired (they finish in order on one stream)
-    std::vector<uint64_t> completed;  // tickets finished since the client last asked
+    std::deque<ba::ServerStep> steps;  // in flight, oldest first (they finish in order on one stream)
+    std::vector<uint64_t> completed;   // tickets finished since the client last asked
     uint32_t inflight = 0;
     unsigned char *staging = nullptr;  // kServerSlots pinned table slots
     uint64_t slot_bytes = 0;
@@ -106,6 +106,20 @@ struct ba_server {
 };
 
 namespace ba {
+
+static ServerJob *server_job(ba_server *s, uint64_t ticket)
+{
+    if (ticket < s->job_base || ticket - s->job_base >= s->jobs.size()) return nullptr;
+    return &s->jobs[ticket - s->job_base];
+}
+
+static void server_trim(ba_server *s)
+{
+    while (!s->jobs.empty() && s->jobs.front().state == BA_JOB_RELEASED) {
+        s->jobs.pop_front();
+        s->job_base++;
+    }
+}
 
 static uint64_t job_output_bytes(const ba_request &r, uint64_t m)
 {
@@ -116,8 +130,8 @@ static uint64_t job_output_bytes(const ba_request &r, uint64_t m)
 // completion time and free their tables.  Steps finish in launch order.
 static int server_retire(ba_server *s)
 {
-    for (; s->first_live < s->steps.size(); s->first_live++) {
-        ServerStep &st = s->steps[s->first_live];
+    while (!s->steps.empty()) {
+        ServerStep &st = s->steps.front();
         const hipError_t q = hipEventQuery(st.ev);
         if (q == hipErrorNotReady) break;
         int rc = hip_check(q);
@@ -125,16 +139,16 @@ static int server_retire(ba_server *s)
         float ms = 0.0f;
         if ((rc = hip_check(hipEventElapsedTime(&ms, s->start, st.ev)))) return rc;
         for (uint64_t j : st.jobs) {
-            s->jobs[j].state = BA_JOB_READY;
-            s->jobs[j].done_ms = ms;
+            ServerJob *J = server_job(s, j);
+            J->state = BA_JOB_READY;
+            J->done_ms = ms;
             s->completed.push_back(j);
         }
         if (st.table_bytes) s->alloc.release(st.table_off, st.table_bytes);
         if (st.slot >= 0) s->free_slots.push_back(st.slot);
         st.slot = -1;
         (void)hipEventDestroy(st.ev);
-        st.ev = nullptr;
-        st.done = true;
+        s->steps.pop_front();
         s->inflight--;
     }
     return BA_OK;
@@ -147,7 +161,7 @@ static int server_launch_step(ba_server *s, uint32_t *launched)
     *launched = 0;
     if (s->free_slots.empty()) return BA_OK;  // every staging slot is in flight
     while (!s->queue.empty()) {
-        ServerJob &J = s->jobs[s->queue.front()];
+        ServerJob &J = *server_job(s, s->queue.front());
         if (J.req.kind == BA_REQ_EDGES && edge_jobs.size() == kServerMaxBatch) break;
         uint64_t off;
         if (!s->alloc.alloc(J.out_bytes, &off)) break;
@@ -159,7 +173,7 @@ static int server_launch_step(ba_server *s, uint32_t *launched)
         *launched = 0;
         // a head job that can never fit an empty arena fails instead of blocking the queue
         if (!s->queue.empty() && s->inflight == 0 && s->alloc.used() == 0) {
-            s->jobs[s->queue.front()].state = BA_JOB_FAILED;
+            server_job(s, s->queue.front())->state = BA_JOB_FAILED;
             s->completed.push_back(s->queue.front());
             s->queue.pop_front();
         }
@@ -173,11 +187,11 @@ static int server_launch_step(ba_server *s, uint32_t *launched)
         if (!s->alloc.alloc(L.bytes, &st.table_off)) {
             // no room for the table: give the outputs back and retry next pump
             for (auto it = deg_jobs.rbegin(); it != deg_jobs.rend(); ++it) {
-                s->alloc.release(s->jobs[*it].out_off, s->jobs[*it].out_bytes);
+                s->alloc.release(server_job(s, *it)->out_off, server_job(s, *it)->out_bytes);
                 s->queue.push_front(*it);
             }
             for (auto it = edge_jobs.rbegin(); it != edge_jobs.rend(); ++it) {
-                s->alloc.release(s->jobs[*it].out_off, s->jobs[*it].out_bytes);
+                s->alloc.release(server_job(s, *it)->out_off, server_job(s, *it)->out_bytes);
                 s->queue.push_front(*it);
             }
             *launched = 0;
@@ -193,7 +207,7 @@ static int server_launch_step(ba_server *s, uint32_t *launched)
         for (int t = 0; t < 3; t++) T[t] = (uint64_t *)(stage + L.o_tile0[t]);
         uint64_t tiles[3] = {0, 0, 0};
         for (uint32_t q = 0; q < ne; q++) {
-            const ServerJob &J = s->jobs[edge_jobs[q]];
+            const ServerJob &J = *server_job(s, edge_jobs[q]);
             I[q].key = make_hash_key(J.req.seed);
             I[q].narrow = 2 * J.m <= ((uint64_t)1 << 32) ? 1u : 0u;
             I[q].div = make_divider(J.req.d ? J.req.d : 1u);
@@ -217,20 +231,16 @@ static int server_launch_step(ba_server *s, uint32_t *launched)
             return rc;
     }
     for (uint64_t j : deg_jobs) {
-        const ServerJob &J = s->jobs[j];
+        const ServerJob &J = *server_job(s, j);
         uint64_t *deg = (uint64_t *)(s->arena + J.out_off);
         if ((rc = ba_degrees(J.req.n, J.req.d, J.req.seed, J.req.first_k, deg, deg + J.req.first_k, s->stream)))
             return rc;
     }
     if ((rc = hip_check(hipEventCreate(&st.ev)))) return rc;
     if ((rc = hip_check(hipEventRecord(st.ev, s->stream)))) return rc;
-    const int64_t sid = (int64_t)s->steps.size();
     for (uint64_t j : edge_jobs) st.jobs.push_back(j);
     for (uint64_t j : deg_jobs) st.jobs.push_back(j);
-    for (uint64_t j : st.jobs) {
-        s->jobs[j].state = BA_JOB_RUNNING;
-        s->jobs[j].step = sid;
-    }
+    for (uint64_t j : st.jobs) server_job(s, j)->state = BA_JOB_RUNNING;
     s->steps.push_back(std::move(st));
     s->inflight++;
     *launched = (uint32_t)(edge_jobs.size() + deg_jobs.size());

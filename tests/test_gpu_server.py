@@ -57,14 +57,16 @@ def test_served_requests_match_the_oracle_under_a_small_arena():
     big = srv.submit_edges(1 << 20, 4, 1)  # 32 MiB of edges: never fits
     tail = srv.submit_degrees(5000, 3, 77, 100)  # queued behind the failing one
     _say("served", len(tickets), "requests")
-    done, steps, order = set(), 0, []
+    done, steps, order, times_seen = set(), 0, [], []
     pending = [x[0] for x in tickets] + [big, tail]
     while len(done) < len(pending):
         steps += srv.pump(max_inflight=2) > 0
         for t in srv.completed():
             order.append(t)
-            st = srv.poll(t)[0]
+            st, ms, _, _ = srv.poll(t)
             if st == ba.JOB_READY:
+                if t < len(tickets):
+                    times_seen.append(ms)
                 if t != tail:
                     _check_result(srv, *tickets[t])
                 else:
@@ -72,13 +74,15 @@ def test_served_requests_match_the_oracle_under_a_small_arena():
                 srv.release(t)
             else:
                 assert st == ba.JOB_FAILED and t == big
+                srv.release(t)  # drops the failed request
             done.add(t)
     assert sorted(order) == sorted(pending) and len(order) == len(pending)
     assert steps >= 5  # the arena forced many continuous-batching steps
     # admission is in arrival order on one stream: completion times never decrease
-    times = [srv.poll(x[0])[1] for x in tickets]
-    assert all(a <= b for a, b in zip(times, times[1:]))
+    assert all(a <= b for a, b in zip(times_seen, times_seen[1:]))
     assert srv.stats() == (0, 0, 0)  # nothing queued, in flight or held
+    with pytest.raises(ba.BAError):
+        srv.poll(tickets[0][0])  # released tickets are gone
     srv.close()
 
 
