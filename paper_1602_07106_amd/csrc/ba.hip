@@ -720,15 +720,21 @@ static int current_device_slot(int *slot)
 
 static constexpr CrcTables kHostCrcTables = make_crc_tables();
 
-template <bool C, bool L>
+template <bool C, bool L, bool N>
 static int launch_model_one(const ModelArgs &a, hipStream_t st)
 {
     uint32_t grid = 0;
-    int rc = persistent_grid(k_gen_model<C, L>, kGenBlock, &grid);
+    int rc = persistent_grid(k_gen_model<C, L, N>, kGenBlock, &grid);
     if (rc) return rc;
     grid = grid_for(a.ntiles, kGenWaves, grid);
     return launch_timed(BA_KT_GEN, st,
-                        [&] { hipLaunchKernelGGL((k_gen_model<C, L>), dim3(grid), dim3(kGenBlock), 0, st, a); });
+                        [&] { hipLaunchKernelGGL((k_gen_model<C, L, N>), dim3(grid), dim3(kGenBlock), 0, st, a); });
+}
+
+template <bool C, bool L>
+static int launch_model_width(const ModelArgs &a, bool narrow, hipStream_t st)
+{
+    return narrow ? launch_model_one<C, L, true>(a, st) : launch_model_one<C, L, false>(a, st);
 }
 
 }  // namespace ba
@@ -1179,8 +1185,10 @@ int ba_generate_model(uint64_t n, uint32_t d, uint64_t seed, uint64_t n0, uint64
     a.edges = edges;
     hipStream_t st = (hipStream_t)stream;
     const bool crc = flags & BA_HASH_CRC, noloops = flags & BA_NO_SELF_LOOPS;
-    if (crc) return noloops ? launch_model_one<true, true>(a, st) : launch_model_one<true, false>(a, st);
-    return noloops ? launch_model_one<false, true>(a, st) : launch_model_one<false, false>(a, st);
+    // every position of the graph (not only of the range) below 2^32: 32-bit arithmetic
+    const bool narrow = 2 * m0 + 2 * m <= ((uint64_t)1 << 32);
+    if (crc) return noloops ? launch_model_width<true, true>(a, narrow, st) : launch_model_width<true, false>(a, narrow, st);
+    return noloops ? launch_model_width<false, true>(a, narrow, st) : launch_model_width<false, false>(a, narrow, st);
 }
 
 const char *ba_strerror(int status)

@@ -72,17 +72,20 @@ __device__ __forceinline__ void fmix_tail(uint32_t &lo, uint32_t &hi, uint32_t h
     hi ^= hi >> 31;
 }
 
-// h(r) for r < 2^32.
-__device__ __forceinline__ uint32_t hash_narrow(uint32_t r, const HashKey &k)
+// umul64hi(fmix64(r XOR key), b) for r, b < 2^32: a value in 0..b-1.
+__device__ __forceinline__ uint32_t hash_narrow_bounded(uint32_t r, uint32_t b, const HashKey &k)
 {
     uint32_t lo = r ^ k.klo;                 // high word of r ^ key is khi
     lo ^= shr64_lo(k.khi, lo, 30);           // z ^= z >> 30, low word
     uint32_t hi = 0;                         // high word folded into c1fold
     fmix_tail(lo, hi, k.c1fold);
-    // umul64hi(z, r) with r < 2^32: (hi*r + mulhi(lo, r)) >> 32
-    uint32_t t = __umulhi(lo, r);
-    return (uint32_t)(mad64(hi, r, t) >> 32);
+    // umul64hi(z, b) with b < 2^32: (hi*b + mulhi(lo, b)) >> 32
+    uint32_t t = __umulhi(lo, b);
+    return (uint32_t)(mad64(hi, b, t) >> 32);
 }
+
+// h(r) for r < 2^32.
+__device__ __forceinline__ uint32_t hash_narrow(uint32_t r, const HashKey &k) { return hash_narrow_bounded(r, r, k); }
 
 // umul64hi(fmix64(r XOR key), b) for any 64-bit r and b >= 1: a value in
 // 0..b-1 (the draw bound b is r itself in the plain model).

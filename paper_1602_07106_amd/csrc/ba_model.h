@@ -22,6 +22,8 @@
 // Included by ba.hip after the chain loop.
 #pragma once
 
+#include <type_traits>
+
 namespace ba {
 
 constexpr uint32_t kCrcPoly = 0x82F63B78u;  // CRC-32C, reflected
@@ -68,9 +70,12 @@ struct ModelArgs {
     uint32_t *edges;
 };
 
-template <bool CRC, bool NOLOOPS>
+// NARROW: every position of the launch (2*m0 + 2*(n-n0)*d) is below 2^32,
+// so positions, bounds and the fmix high product stay 32-bit.
+template <bool CRC, bool NOLOOPS, bool NARROW>
 __global__ __launch_bounds__(kGenBlock) void k_gen_model(ModelArgs a)
 {
+    using R = typename std::conditional<NARROW, uint32_t, uint64_t>::type;
     __shared__ uint32_t stage_all[kGenWaves][kTile];
     __shared__ uint32_t crc_t[CRC ? 8 : 1][256];
     if constexpr (CRC) {
@@ -81,36 +86,37 @@ __global__ __launch_bounds__(kGenBlock) void k_gen_model(ModelArgs a)
     const uint32_t wv = threadIdx.x / kWave;
     uint32_t *stage = stage_all[wv];
     const uint64_t wstride = (uint64_t)gridDim.x * kGenWaves;
-    const uint64_t P0 = a.P0;
+    const R P0 = (R)a.P0;
 
-    // draw bound of the edge whose second endpoint sits at odd r >= P0
-    auto bound = [&](uint64_t r) -> uint64_t {
-        if constexpr (NOLOOPS) {
-            const uint64_t node = div64((r - P0) >> 1, a.div);  // (r - P0 - 1)/2 = edge index
-            return P0 + 2 * (uint64_t)a.div.d * node;
-        } else {
-            return r;
-        }
+    // floor(x / d) in the width of the launch
+    auto divd = [&](R x) -> R {
+        if constexpr (NARROW) return div32(x, a.div);
+        else return div64(x, a.div);
     };
-    auto hash = [&](uint64_t r) -> uint64_t {
-        const uint64_t b = bound(r);
+    // draw bound of the edge whose second endpoint sits at odd r >= P0
+    auto bound = [&](R r) -> R {
+        if constexpr (NOLOOPS) return P0 + 2 * (R)a.div.d * divd((r - P0) >> 1);  // (r-P0-1)/2 = edge index
+        else return r;
+    };
+    auto hash = [&](R r) -> R {
+        const R b = bound(r);
         if constexpr (CRC) {
-            const uint32_t c0 = crc32c_u64(crc_t, 0u, r ^ a.key64);
-            return (((uint64_t)c0 << 32) + (uint64_t)(c0 ^ a.k1)) % b;
+            const uint32_t c0 = crc32c_u64(crc_t, 0u, (uint64_t)r ^ a.key64);
+            return (R)(((((uint64_t)c0 << 32) + (uint64_t)(c0 ^ a.k1))) % (uint64_t)b);
+        } else if constexpr (NARROW) {
+            return hash_narrow_bounded(r, b, a.key);
         } else {
             return hash_bounded(r, b, a.key);
         }
     };
-    auto stop = [&](uint64_t r) { return r < P0 || !(r & 1); };
-    auto node = [&](uint64_t r) -> uint32_t {
-        return r < P0 ? a.S[r] : (uint32_t)(a.n0 + div64((r - P0) >> 1, a.div));
-    };
+    auto stop = [&](R r) { return r < P0 || !(r & 1); };
+    auto node = [&](R r) -> uint32_t { return r < P0 ? a.S[r] : (uint32_t)(a.n0 + divd((r - P0) >> 1)); };
 
     for (uint64_t tile = (uint64_t)blockIdx.x * kGenWaves + wv; tile < a.ntiles; tile += wstride) {
         const uint64_t off = tile * kTile;
         const uint32_t tn = (uint32_t)min((uint64_t)kTile, a.count - off);
         const uint64_t ibase = a.begin + off;
-        chain_tile_until(stage, tn, lane, P0 + 2 * ibase + 1, hash, stop, node);
+        chain_tile_until(stage, tn, lane, (R)(a.P0 + 2 * ibase + 1), hash, stop, node);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -118,8 +124,8 @@ __global__ __launch_bounds__(kGenBlock) void k_gen_model(ModelArgs a)
         const bool vec16 = (((uintptr_t)out) & 15) == 0;
         for (uint32_t j = 2 * lane; j < tn; j += 2 * kWave) {
             const uint2 s = *reinterpret_cast<const uint2 *>(stage + j);
-            const uint32_t u0 = (uint32_t)(a.n0 + div64(ibase + j, a.div));
-            const uint32_t u1 = (uint32_t)(a.n0 + div64(ibase + j + 1, a.div));
+            const uint32_t u0 = (uint32_t)(a.n0 + divd((R)(ibase + j)));
+            const uint32_t u1 = (uint32_t)(a.n0 + divd((R)(ibase + j + 1)));
             if (vec16)
                 store_pair<true>(out, j, tn, u0, s.x, u1, s.y);
             else

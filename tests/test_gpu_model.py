@@ -94,3 +94,18 @@ def test_model_with_64_bit_positions(no_loops, h):
         torch.cuda.synchronize()
         ref, _ = oracle.model_edges_range(n0, m0, S, d, seed, _oflags(no_loops, h), b, 1000)
         assert np.array_equal(out.cpu().numpy().view(np.uint32), ref)
+
+
+@pytest.mark.parametrize("m0", [0, 4])
+def test_model_at_the_32_bit_position_boundary(m0):
+    # 2*m0 + 2*(n-n0)*d = 2^32 exactly (32-bit path) or just past it (64-bit path)
+    n0, d, seed = 3, 16, 8
+    n = n0 + (1 << 27)
+    S, St = _seed_graph(n0, m0, 12)
+    m = (n - n0) * d
+    for b in [0, m - 2000]:
+        _say("model boundary", m0, b)
+        out = ba.generate_model(n, d, seed, n0=n0, seed_edges=St if m0 else None, begin=b, count=2000)
+        torch.cuda.synchronize()
+        ref, _ = oracle.model_edges_range(n0, m0, S, d, seed, 0, b, 2000)
+        assert np.array_equal(out.cpu().numpy().view(np.uint32), ref)
