@@ -116,12 +116,17 @@ def kernel_rooflines(per_launch_s: dict) -> dict:
     out = {}
     t = per_launch_s.get("gen")
     if t:
+        # both bounds of the chain kernel; the binding one is the longer
         cyc = (HASH_PER_EDGE * CYCLES_PER_HASH + CYCLES_PER_EDGE) * M
-        alu = cyc / t
-        hbm = GEN_BYTES_PER_EDGE * M / t
-        out["gen"] = {"bound": "alu", "achieved": alu / 1e12, "peak": VALU_PEAK / 1e12, "unit": "Tlane-cycles/s",
-                      "frac": alu / VALU_PEAK, "hbm_frac": hbm / HBM_PEAK, "alg_bytes": GEN_BYTES_PER_EDGE * M,
-                      "alg_cycles": cyc}
+        nbytes = GEN_BYTES_PER_EDGE * M
+        alu, hbm = cyc / t, nbytes / t
+        if nbytes / HBM_PEAK >= cyc / VALU_PEAK:
+            out["gen"] = {"bound": "hbm", "achieved": hbm / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                          "frac": hbm / HBM_PEAK, "alu_frac": alu / VALU_PEAK}
+        else:
+            out["gen"] = {"bound": "alu", "achieved": alu / 1e12, "peak": VALU_PEAK / 1e12, "unit": "Tlane-cycles/s",
+                          "frac": alu / VALU_PEAK, "hbm_frac": hbm / HBM_PEAK}
+        out["gen"].update({"alg_bytes": nbytes, "alg_cycles": cyc})
     for k, nbytes in (("part", PART_BYTES_PER_EDGE * M), ("hist", HIST_BYTES)):
         t = per_launch_s.get(k)
         if t:
@@ -129,6 +134,21 @@ def kernel_rooflines(per_launch_s: dict) -> dict:
             out[k] = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                       "frac": bw / HBM_PEAK, "alg_bytes": nbytes}
     return out
+
+
+def batch_roofline(cyc: float, nbytes: float, t: float, ms_per_step: float, launches: int) -> dict:
+    """Binding roofline (the longer of the ALU and HBM times) of one pass of
+    the batched kernel over all rounds."""
+    alu, hbm = cyc / t / VALU_PEAK, nbytes / t / HBM_PEAK
+    if nbytes / HBM_PEAK >= cyc / VALU_PEAK:
+        r = {"bound": "hbm", "achieved": round(nbytes / t / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+             "frac": round(hbm, 4), "alu_frac": round(alu, 4)}
+    else:
+        r = {"bound": "alu", "achieved": round(cyc / t / 1e12, 2), "peak": round(VALU_PEAK / 1e12, 2),
+             "unit": "Tlane-cycles/s", "frac": round(alu, 4), "hbm_frac": round(hbm, 4)}
+    r.update({"traffic": None, "kernel": "k_gen_batch", "kernel_ms_per_step": round(ms_per_step, 3),
+              "launches": launches, "alg_bytes_per_step": nbytes, "alg_lane_cycles_per_step": cyc})
+    return r
 
 
 def bench_batch(args) -> int:
@@ -212,10 +232,7 @@ def bench_batch(args) -> int:
                    "edges": total, "rounds": rounds, "shape": list(ba.batch_shape(shape))},
         "single_graph_edges_per_s": single_rate,
         "batched_over_single": value / single_rate,
-        "roofline": {"bound": "alu", "achieved": round(cyc / t_launch / 1e12, 2), "peak": round(VALU_PEAK / 1e12, 2),
-                     "unit": "Tlane-cycles/s", "frac": round(cyc / t_launch / VALU_PEAK, 4), "traffic": None,
-                     "kernel": "k_gen_batch", "kernel_ms_per_step": round(gen_ms / args.steps, 3),
-                     "launches": gen_n, "hbm_frac": round(8.0 * total / t_launch / HBM_PEAK, 4)},
+        "roofline": batch_roofline(cyc, 8.0 * total, t_launch, gen_ms / args.steps, gen_n),
     }
     print(json.dumps(line), flush=True)
     return 0
@@ -379,8 +396,9 @@ def main() -> int:
         e = {"ms_per_launch": round(ms / n, 4), "launches": n, "share_of_step": round(ms / gpu_ms, 4)}
         if k in roofs:
             e.update({"bound": roofs[k]["bound"], "frac": round(roofs[k]["frac"], 4)})
-            if "hbm_frac" in roofs[k]:
-                e["hbm_frac"] = round(roofs[k]["hbm_frac"], 4)
+            for f in ("hbm_frac", "alu_frac"):
+                if f in roofs[k]:
+                    e[f] = round(roofs[k][f], 4)
         kernels[k] = e
     dom = max(roofs, key=lambda k: kt[k][0])
     r = roofs[dom]
@@ -390,7 +408,15 @@ def main() -> int:
             "alg_bytes_per_launch": r["alg_bytes"]}
     if "alg_cycles" in r:
         roof["alg_lane_cycles_per_launch"] = r["alg_cycles"]
-        roof["hbm_frac"] = round(r["hbm_frac"], 4)
+        for f in ("hbm_frac", "alu_frac"):
+            if f in r:
+                roof[f] = round(r[f], 4)
+    # the whole step against the method's own bytes (edge pairs + degree
+    # array: 8 B per edge + 4 B per node) and its hash work
+    step_s = ms_per_step / 1e3
+    path = {"alg_bytes_per_edge": (8.0 * M + 4.0 * N) / M,
+            "hbm_frac": round((8.0 * M + 4.0 * N) / step_s / HBM_PEAK, 4),
+            "alu_frac": round((HASH_PER_EDGE * CYCLES_PER_HASH + CYCLES_PER_EDGE) * M / step_s / VALU_PEAK, 4)}
 
     line = {
         "metric": "edges/s at n=2^26,d=16 (bit-exact)",
@@ -409,6 +435,7 @@ def main() -> int:
                                "uint32 degree array", "edges": M, "n": N, "d": D, "seed": SEED},
         "roofline": roof,
         "kernels": kernels,
+        "path": path,
         "wall_s": round(wall, 3),
     }
     if not args.no_cpu_baseline:
