@@ -189,3 +189,38 @@ def test_degrees_in_several_passes_with_heavy_sub_buckets():
     edges, deg2 = ba.generate(n, d, seed, degrees=True)
     torch.cuda.synchronize()
     assert np.array_equal(_u32(deg2).astype(np.uint64), ref)
+
+
+def test_extreme_parameters_sampled():
+    # the largest uint32 graph (IDs up to 2^32 - 1), a huge d (one divisor
+    # for 2^31 - 1 edges per node), d = 1 with 64-bit positions, extreme seeds
+    cases = [((1 << 32), 2, 5), ((1 << 32), 1, M64), (3, (1 << 31) - 1, 0), (5, (1 << 30) + 7, 77),
+             ((1 << 33) + 3, 1, 9)]
+    for n, d, seed in cases:
+        m = n * d
+        for b in [0, m // 2 - 1000, m - 2000]:
+            _say("extreme", n, d, seed, b)
+            ref, _ = oracle.edges_range(d, seed, b, 2000)
+            if n <= (1 << 32):
+                out = ba.generate_range(n, d, seed, b, 2000)
+                torch.cuda.synchronize()
+                assert np.array_equal(_u32(out), ref.astype(np.uint32).reshape(-1))
+            out64 = ba.generate_range_u64(n, d, seed, b, 2000)
+            torch.cuda.synchronize()
+            assert np.array_equal(_u64(out64), ref.reshape(-1))
+
+
+def test_range_degrees_starting_and_ending_inside_a_node():
+    # a range whose first and last edges are not node boundaries: the first
+    # endpoints of the partial nodes count only the edges in the range
+    n, d, seed = 20000, 7, 3
+    m = n * d
+    E, _ = oracle.bb_generate(n, d, seed)
+    for b, c in [(3, 1000), (12345, 54321), (m - 5, 5), (6, 1)]:
+        _say("partial-node range degrees", b, c)
+        deg = torch.zeros(n, dtype=torch.int32, device="cuda")
+        out = ba.generate_range(n, d, seed, b, c, deg=deg)
+        torch.cuda.synchronize()
+        assert np.array_equal(_u32(out), E[2 * b:2 * (b + c)])
+        ref = np.bincount(E[2 * b:2 * (b + c)].astype(np.int64), minlength=n)
+        assert np.array_equal(_u32(deg).astype(np.int64), ref)
