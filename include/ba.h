@@ -188,7 +188,7 @@ int ba_kernel_timing_read(double *ms, uint64_t *launches);
  * shapes 0..BA_BATCH_SHAPES-1) on the given batch and keeps the fastest for
  * the current device; later ba_batch_launch calls on that device use it
  * (ba_batch_current_shape reports its index, ba_batch_shape_dims the tile
- * and block of any index).  Without tuning the shape is 0: 2048-edge tiles,
+ * and block of any index).  Without tuning the shape is 0: 1024-edge tiles,
  * 4 waves per block.  The tuner's own launches write the batch's edges too.
  * ba_batch_launch_shape launches with an explicit shape (same output).
  *

@@ -48,7 +48,7 @@ namespace ba {
 constexpr int kWave = 64;
 constexpr int kGenBlock = 256;  // 4 waves
 constexpr int kGenWaves = kGenBlock / kWave;
-constexpr uint32_t kTile = 2048;  // edges per wave tile (8 KiB of LDS per wave)
+constexpr uint32_t kTile = 1024;  // edges per wave tile (4 KiB of LDS per wave; 8 waves/SIMD fit)
 
 struct GenArgs {
     HashKey key;
@@ -665,7 +665,7 @@ struct BatchShape {
     int tile_idx;  // index into kBatchTiles
     uint32_t waves;
 };
-constexpr BatchShape kBatchShapes[] = {{1, 4}, {0, 4}, {2, 4}, {0, 8}, {1, 8}};
+constexpr BatchShape kBatchShapes[] = {{0, 4}, {1, 4}, {2, 4}, {0, 8}, {1, 8}};
 constexpr int kBatchShapeCount = sizeof(kBatchShapes) / sizeof(kBatchShapes[0]);
 constexpr int kMaxDevices = 64;
 // Chosen shape per device: written only by ba_batch_autotune, -1 = default (shape 0).
@@ -696,8 +696,8 @@ static int launch_batch(int shape, const ba_batch_info *info, const void *ws, ui
     a.edges = edges;
     if (a.tiles == 0) return BA_OK;
     switch (shape) {
-    case 0: return launch_batch_shape<2048, 4>(a, st);
-    case 1: return launch_batch_shape<1024, 4>(a, st);
+    case 0: return launch_batch_shape<1024, 4>(a, st);
+    case 1: return launch_batch_shape<2048, 4>(a, st);
     case 2: return launch_batch_shape<4096, 4>(a, st);
     case 3: return launch_batch_shape<1024, 8>(a, st);
     default: return launch_batch_shape<2048, 8>(a, st);

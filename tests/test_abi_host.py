@@ -172,7 +172,7 @@ def test_batch_host_validation_without_gpu():
                              ctypes.addressof(info), None) == ba.BA_EINVAL
     assert L.ba_batch_workspace_bytes(4096) >= 4096 * 64 + 3 * 4097 * 8
     assert L.ba_batch_launch_shape(ctypes.addressof(info), None, None, 0, 5, None) == ba.BA_EINVAL
-    assert [ba.batch_shape(k)[1:] for k in range(ba.BATCH_SHAPES)] == [(2048, 4), (1024, 4), (4096, 4), (1024, 8),
+    assert [ba.batch_shape(k)[1:] for k in range(ba.BATCH_SHAPES)] == [(1024, 4), (2048, 4), (4096, 4), (1024, 8),
                                                                        (2048, 8)]
 
 
