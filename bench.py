@@ -327,14 +327,88 @@ def bench_served(args) -> int:
     return 0
 
 
+# Streaming workload: n=2^30, d=64, seed=42, degrees of nodes 0..10^5-1 and
+# the edge checksum over all 2^36 edges (64-bit positions, nothing stored).
+# Algorithmic VALU issue cycles: 22.5 per evaluation of the general hash
+# (7 multiply-class + 3 alignbit + 2 add3 at 1, 9 xor/shift at 0.5, parity
+# test 1) at the ideal-hash mean of evaluations per edge, plus 17 per edge
+# (two 64-bit divisions by d and the checksum word's 64-bit product).
+STREAM = (1 << 30, 64, 42, 100000)
+STREAM_CYCLES_PER_HASH = 22.5
+STREAM_CYCLES_PER_EDGE = 17.0
+
+
+def bench_stream(args) -> int:
+    import torch
+
+    import paper_1602_07106_amd as ba
+
+    n, d, seed, k = STREAM
+    m = n * d
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    for _ in range(args.warmup):
+        ba.degrees(n, d, seed, k)
+    torch.cuda.synchronize()
+    ba.kernel_timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        ba.degrees(n, d, seed, k)
+    e1.record()
+    torch.cuda.synchronize()
+    kt = ba.kernel_timing_read()
+    ba.kernel_timing(False)
+    ms = e0.elapsed_time(e1) / args.steps
+    st_ms, st_n = kt["stream"]
+    t = st_ms / st_n / 1e3
+    hashes = m * (2.0 - 1.77 / m ** 0.5)
+    cyc = hashes * STREAM_CYCLES_PER_HASH + m * STREAM_CYCLES_PER_EDGE
+    line = {
+        "metric": "edges/s, streamed first-10^5 degrees at n=2^30, d=64",
+        "value": m / (ms / 1e3),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic (the generator is the workload: n, d, seed)",
+        "config": {"workload": "streamed degrees of nodes 0..99999 + edge checksum, n=2^30, d=64, seed=42, "
+                               "2^36 edges, nothing stored", "edges": m},
+        "roofline": {"bound": "alu", "achieved": round(cyc / t / 1e12, 2), "peak": round(VALU_PEAK / 1e12, 2),
+                     "unit": "Tlane-cycles/s", "frac": round(cyc / t / VALU_PEAK, 4), "traffic": None,
+                     "kernel": "k_stream (64-bit positions)", "kernel_ms": round(t * 1e3, 3), "launches": st_n,
+                     "alg_lane_cycles_per_launch": cyc},
+    }
+    if not args.no_cpu_baseline:
+        import time as _t
+
+        import oracle
+
+        c = 1 << 28
+        t0 = _t.perf_counter()
+        oracle.stream(d, seed, 0, c, k)
+        dt = _t.perf_counter() - t0
+        line["cpu_baseline"] = {"value": c / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                                "sample": "first 2^28 edges of the same graph, streamed degrees + checksum, %.1f s" % dt}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["graph", "batch", "served"], default="graph",
+    ap.add_argument("--workload", choices=["graph", "batch", "served", "stream"], default="graph",
                     help="graph: the n=2^26, d=16 graph with degrees (default); batch: 4096 graphs; "
-                         "served: a 4000-request trace through the continuous-batching server")
+                         "served: a 4000-request trace through the continuous-batching server; "
+                         "stream: streamed first-10^5 degrees at n=2^30, d=64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers (reference for HBM counters)")
@@ -349,6 +423,8 @@ def main() -> int:
         return bench_batch(args)
     if args.workload == "served":
         return bench_served(args)
+    if args.workload == "stream":
+        return bench_stream(args)
 
     import torch
 
