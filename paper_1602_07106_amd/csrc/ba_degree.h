@@ -424,10 +424,16 @@ __global__ __launch_bounds__(kHBlock) void k_deg_hist(DegArgs a)
 
     for (uint32_t x = threadIdx.x; x < kSub; x += kHBlock) cnt[x] = 0;
     __syncthreads();
-    // each wave takes whole regions; 8 entries per 16-byte load where aligned
+    // each wave takes whole regions (p0 + wv, p0 + wv + 16, ...); lane j
+    // fetches the fill of the wave's j-th region up front (at most
+    // kPBlocksMax / 16 = 64 regions a wave), so no region waits on a load of
+    // its own length; 8 entries per 16-byte load where aligned
+    static_assert(kPBlocksMax / (kHBlock / 64) <= 64, "one region fill per lane");
     const uint32_t lane = __lane_id(), wv = threadIdx.x / 64;
-    for (uint32_t p = p0 + wv; p < p1; p += kHBlock / 64) {
-        const uint32_t n = min(fill[(uint64_t)p * N + g], cp);
+    const uint32_t pl = p0 + wv + (kHBlock / 64) * lane;
+    const uint32_t nl = pl < p1 ? min(fill[(uint64_t)pl * N + g], cp) : 0u;
+    for (uint32_t p = p0 + wv, jr = 0; p < p1; p += kHBlock / 64, jr++) {
+        const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)nl, (int)jr);  // jr is wave-uniform
         const uint16_t *src = L + base + (uint64_t)p * cp;
         const uint32_t head = min(n, (uint32_t)((8 - (((uintptr_t)src >> 1) & 7)) & 7));
         if (lane < head) atomicAdd(&cnt[src[lane]], 1u);
