@@ -139,6 +139,25 @@ int ba_degrees_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin,
                      uint64_t *xor_checksum, void *stream);
 
 /*
+ * Which LDS counter tier the streaming degree kernel uses (process-wide,
+ * host only; results are identical either way, only speed differs):
+ *   BA_TIER_AUTO : the default; BA_TIER_64K when first_k > 16384 and the
+ *                  targets expected in [16384, min(first_k, 65536)), about
+ *                  (sqrt(min(first_k, 65536)) - 128) / sqrt(n) of them,
+ *                  exceed 1.8% (small n), else BA_TIER_16K.
+ *   BA_TIER_16K  : 32-bit LDS counters for nodes below 16384 (64 KiB per
+ *                  block, two blocks per compute unit); every other target
+ *                  below first_k is a global atomic.
+ *   BA_TIER_64K  : 16-bit LDS counters for nodes below 65536 (128 KiB per
+ *                  block, one block per compute unit), moved to the global
+ *                  count 32768 at a time as they fill.
+ * ba_degrees_tier sets the tier (BA_EINVAL for another value) and, when
+ * previous is not NULL, stores the one it replaces.
+ */
+enum { BA_TIER_AUTO = 0, BA_TIER_16K = 16, BA_TIER_64K = 64 };
+int ba_degrees_tier(int tier, int *previous);
+
+/*
  * Measurement hook for benchmarks (not needed to generate graphs).
  * ba_kernel_timing(1) makes every later call on this host thread record a
  * HIP event pair on its stream around each kernel it launches, tagged with

@@ -39,6 +39,7 @@ __all__ = [
     "kernel_timing_read",
     "degrees",
     "degrees_range",
+    "degrees_tier",
     "Batch",
     "batch_plan_rounds",
     "batch_shape",
@@ -74,6 +75,7 @@ _SIGS = {
     "ba_generate_range_u64": (_int, [_u64, _u32, _u64, _u64, _u64, _p, _p]),
     "ba_degrees": (_int, [_u64, _u32, _u64, _u64, _p, _p, _p]),
     "ba_degrees_range": (_int, [_u64, _u32, _u64, _u64, _u64, _u64, _p, _p, _p]),
+    "ba_degrees_tier": (_int, [_int, _p]),
     "ba_strerror": (ctypes.c_char_p, [_int]),
     "ba_last_hip_error": (_int, []),
     "ba_host_divide": (_int, [_u32, _p, _p, _u64]),
@@ -299,6 +301,18 @@ def degrees_range(
             "ba_degrees_range",
             lib().ba_degrees_range(n, d, seed, begin, count, first_k, _ptr(deg), _ptr(cs), _stream(dev)),
         )
+
+
+TIER_AUTO, TIER_16K, TIER_64K = 0, 16, 64
+
+
+def degrees_tier(tier: int) -> int:
+    """Select the LDS counter tier of the streaming degree kernel
+    (TIER_AUTO, TIER_16K or TIER_64K; process-wide, results identical) and
+    return the previous setting."""
+    prev = ctypes.c_int(0)
+    _check("ba_degrees_tier", lib().ba_degrees_tier(tier, ctypes.byref(prev)))
+    return prev.value
 
 
 class BatchInfo(ctypes.Structure):

@@ -186,3 +186,17 @@ def test_model_argument_checks_without_gpu():
     assert L.ba_generate_model(100, 2, 1, 10, 3, None, 0, 0, 1, 16, None) == ba.BA_EINVAL  # seed edges missing
     assert L.ba_generate_model((1 << 32) + 1, 1, 1, 0, 0, None, 0, 0, 0, None, None) == ba.BA_ERANGE
     assert L.ba_generate_model(100, 2, 1, 10, 0, None, 0, 5, 0, None, None) == ba.BA_OK  # empty range
+
+
+def test_degrees_tier_setting():
+    import paper_1602_07106_amd as ba
+    prev = ba.degrees_tier(ba.TIER_64K)
+    try:
+        assert ba.degrees_tier(ba.TIER_16K) == ba.TIER_64K
+        assert ba.degrees_tier(ba.TIER_AUTO) == ba.TIER_16K
+        for bad in (1, 32, -1, 65):
+            with pytest.raises(ba.BAError):
+                ba.degrees_tier(bad)
+        assert ba.degrees_tier(ba.TIER_AUTO) == ba.TIER_AUTO
+    finally:
+        ba.degrees_tier(prev)

@@ -145,6 +145,50 @@ def test_streaming_ranges_accumulate_including_wide_positions():
     assert (int(cs.item()) & M64) == rcs
 
 
+@pytest.fixture
+def _tier():
+    prev = ba.degrees_tier(ba.TIER_AUTO)
+    yield
+    ba.degrees_tier(prev)
+
+
+@pytest.mark.parametrize("tier", [ba.TIER_16K, ba.TIER_64K])
+@pytest.mark.parametrize("n,d,seed,k", [(100000, 4, 1, 100000), (20000, 5, 3, 1000), (70001, 9, 77, 65537),
+                                        (3000, 2, 5, 3000)])
+def test_streaming_degrees_on_either_lds_tier(_tier, tier, n, d, seed, k):
+    """Both LDS counter tiers give the oracle's counts, whichever holds the
+    node (LDS word or global atomic) and at the 65536-node tier edge."""
+    _say("degrees tier", tier, n, d, seed, k)
+    ba.degrees_tier(tier)
+    deg, cs = ba.degrees(n, d, seed, k)
+    torch.cuda.synchronize()
+    E, _ = oracle.bb_generate(n, d, seed)
+    assert np.array_equal(_u64(deg), oracle.count_degrees(E, n)[:k])
+    assert cs == oracle.checksum_E(E)
+
+
+@pytest.mark.parametrize("tier", [ba.TIER_16K, ba.TIER_64K])
+@pytest.mark.parametrize("begin,d", [(0, 1 << 24), ((1 << 31) - (1 << 12), 1 << 31)])
+def test_streaming_degrees_of_two_very_heavy_nodes(_tier, tier, begin, d):
+    """n = 2 with a huge d: about 2^25 targets land on nodes 0 and 1, so every
+    block of the 64K tier takes the 16-bit counters of both halves of one LDS
+    word past 0x7FFF several times (up to the 32768-per-round maximum).  The
+    second case runs on 64-bit positions (edges straddling 2^31, the
+    boundary between nodes 0 and 1)."""
+    n, count, k = 2, 1 << 25, 2
+    _say("heavy degrees", tier, begin, d)
+    ba.degrees_tier(tier)
+    deg = torch.zeros(k, dtype=torch.int64, device="cuda")
+    cs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ba.degrees_range(n, d, seed := 11, begin, count, k, deg, cs)
+    torch.cuda.synchronize()
+    ref, rcs, _ = oracle.stream(d, seed, begin, count, k)
+    got = _u64(deg)
+    assert got.sum() == 2 * count
+    assert np.array_equal(got, ref)
+    assert (int(cs.item()) & M64) == rcs
+
+
 def test_degrees_through_the_stream_ordered_allocator():
     # ba_generate without a workspace takes one from hipMallocAsync
     n, d, seed = 70000, 6, 21
