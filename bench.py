@@ -52,6 +52,8 @@ KERNEL_NAMES = {
     "hist": "k_deg_hist (LDS histograms into deg)",
 }
 PROFILE = os.path.join(ROOT, "profiles", "pipeline_n2e26_d16_hbm_traffic.md")
+# Files holding the pipeline's kernels and the host code that launches them:
+# the committed counter summary counts only while they are unchanged.
 KERNEL_SOURCES = [
     os.path.join(ROOT, "paper_1602_07106_amd", "csrc", f) for f in ("ba.hip", "ba_device.h", "ba_degree.h")
 ]

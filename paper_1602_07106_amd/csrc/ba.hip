@@ -24,10 +24,10 @@
 // radix partition and LDS histograms; first endpoints contribute exactly d
 // per node, in closed form.
 //
-// The streaming kernel (paper Section 3) stores nothing: each finished edge
-// updates the degree counts of the first k nodes (an LDS-privatised table for
-// the hottest low IDs, 64-bit global atomics above) and a per-lane XOR
-// checksum, reduced per wave at the end.
+// The streaming kernels (paper Section 3, ba_stream.h) store nothing: each
+// finished edge updates the degree counts of the first k nodes (an
+// LDS-privatised table for the hottest low IDs, 64-bit global atomics above)
+// and a per-lane XOR checksum, reduced per wave at the end.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -296,210 +296,6 @@ __global__ void k_first_endpoints(T *deg, uint64_t v0, uint64_t v1, uint64_t b, 
     }
 }
 
-// ------------------------------------------------------------ streaming
-
-constexpr int kStreamBlock = 1024;  // 16 waves share one LDS degree table
-constexpr int kStreamWaves = kStreamBlock / kWave;
-constexpr uint32_t kLdsNodes = 16384;  // LDS-privatised degree counters per block
-
-struct StreamArgs {
-    HashKey key;
-    Divider div;
-    uint64_t begin, count;
-    uint64_t per_wave;  // edges per wave (multiple of 64)
-    uint64_t rounds;    // packed tier: barriers every wave takes
-    uint64_t k;         // first_k
-    uint32_t klds;      // min(k, kLdsNodes)
-    uint64_t *deg;      // first_k uint64 (second endpoints added here)
-    uint64_t *cs;       // nullable
-};
-
-template <bool NARROW>
-__global__ __launch_bounds__(kStreamBlock) void k_stream(StreamArgs a)
-{
-    __shared__ uint32_t cnt[kLdsNodes];
-    for (uint32_t v = threadIdx.x; v < a.klds; v += kStreamBlock) cnt[v] = 0;
-    __syncthreads();
-
-    const uint32_t lane = __lane_id();
-    const uint64_t gw = (uint64_t)blockIdx.x * kStreamWaves + threadIdx.x / kWave;
-    const uint64_t w0 = gw * a.per_wave;
-    uint64_t xs = 0;
-    if (w0 < a.count) {
-        const uint64_t wn = min(a.per_wave, a.count - w0);
-        const uint64_t ibase = a.begin + w0;
-        uint64_t li = lane;
-        bool active = li < wn;
-        uint64_t next = kWave, remaining = wn;
-        uint64_t r = 2 * (ibase + li) + 1;
-        while (remaining) {
-            if constexpr (NARROW)
-                r = hash_narrow((uint32_t)r, a.key);
-            else
-                r = hash_wide(r, a.key);
-            const bool done = active && !(r & 1u);
-            const uint64_t dm = __ballot(done);
-            if (done) {
-                const uint64_t i = ibase + li;
-                const uint64_t v = NARROW ? (uint64_t)div32((uint32_t)(r >> 1), a.div)
-                                          : div64(r >> 1, a.div);
-                const uint64_t u = NARROW ? (uint64_t)div32((uint32_t)i, a.div) : div64(i, a.div);
-                if (v < a.klds)
-                    atomicAdd(&cnt[v], 1u);
-                else if (v < a.k)
-                    __hip_atomic_fetch_add(a.deg + v, (uint64_t)1, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                xs ^= ((u << 32) + v) * (2 * i + 1);
-                li = next + lane_rank(dm);
-                active = li < wn;
-                r = 2 * (ibase + li) + 1;
-            }
-            const uint32_t nd = (uint32_t)__popcll(dm);
-            next += nd;
-            remaining -= nd;
-        }
-    }
-    if (a.cs) {
-        for (int o = 32; o > 0; o >>= 1) xs ^= __shfl_xor(xs, o);
-        if (lane == 0 && xs) __hip_atomic_fetch_xor(a.cs, xs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    for (uint32_t v = threadIdx.x; v < a.klds; v += kStreamBlock) {
-        const uint32_t c = cnt[v];
-        if (c) __hip_atomic_fetch_add(a.deg + v, (uint64_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-// k_stream with a wider LDS tier for first_k > 16384: nodes 0..65535 count in
-// 16-bit counters, two to an LDS word (node v: word v >> 1, half v & 1;
-// 128 KiB, one block per compute unit), so only targets in [65536, first_k)
-// need global atomics.
-//
-// A 16-bit counter could wrap, so the block synchronises in rounds.  Chains
-// in flight carry across a round boundary; a wave takes its next barrier as
-// soon as it has handed out kStreamRoundClaims more edges, so it finishes at
-// most kStreamRoundClaims + 63 edges between two barriers, and the block at
-// most 16 * 2047 = 32752.  A counter below 0x8000 at a barrier therefore
-// stays at or below 0xFFFF until the next one; the lane whose increment takes
-// it from 0x7FFF to 0x8000 moves those 32768 counts to the global degree
-// before its wave's next barrier.  Every counter is below 0x8000 again at
-// each barrier, and the counts are exact.  Waves that run out of edges early
-// take their remaining barriers at the end, so all take a.rounds of them.
-constexpr uint32_t kPackedNodes = 65536;
-constexpr uint32_t kStreamRoundClaims = 1984;
-static_assert(kStreamWaves * (kStreamRoundClaims + kWave - 1) <= 0x8000, "a round must not wrap a 16-bit counter");
-
-template <bool NARROW>
-__global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
-{
-    __shared__ uint32_t cnt[kPackedNodes / 2];  // node v: word v >> 1, half v & 1
-    for (uint32_t w = threadIdx.x; w < kPackedNodes / 2; w += kStreamBlock) cnt[w] = 0;
-    __syncthreads();
-    using R = typename std::conditional<NARROW, uint32_t, uint64_t>::type;
-    const uint32_t lane = __lane_id();
-    const uint64_t gw = (uint64_t)blockIdx.x * kStreamWaves + threadIdx.x / kWave;
-    const uint64_t w0 = gw * a.per_wave;
-    // edges of this wave (per_wave < 2^32: the host splits larger launches)
-    const uint32_t tot = w0 < a.count ? (uint32_t)min(a.per_wave, a.count - w0) : 0u;
-    const uint64_t ibase = a.begin + w0;
-    const R rbase = (R)(2 * ibase + 1);
-    const uint32_t ktier = a.klds;  // min(first_k, 65536)
-    uint64_t xs = 0;
-
-    // The value a lane's last LDS increment returned is examined at its next
-    // finished edge (or before its wave's next barrier), so the wave does not
-    // wait for the atomic's result right after issuing it.
-    constexpr uint32_t kNone = 0xFFFFFFFFu;
-    uint32_t pend_old = 0, pend_v = kNone;
-    auto settle = [&]() {
-        if (pend_v != kNone) {
-            const uint32_t sh = (pend_v & 1u) << 4;
-            if (((pend_old >> sh) & 0xFFFFu) == 0x7FFFu) {
-                atomicSub(&cnt[pend_v >> 1], 0x8000u << sh);
-                __hip_atomic_fetch_add(a.deg + pend_v, (uint64_t)0x8000, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            pend_v = kNone;
-        }
-    };
-    auto hash = [&](R r) -> R {
-        if constexpr (NARROW) return hash_narrow(r, a.key);
-        else return hash_wide(r, a.key);
-    };
-    auto finish = [&](uint32_t li, R r) {
-        const uint64_t i = ibase + li;
-        const uint64_t v = NARROW ? (uint64_t)div32((uint32_t)(r >> 1), a.div) : div64(r >> 1, a.div);
-        const uint64_t u = NARROW ? (uint64_t)div32((uint32_t)i, a.div) : div64(i, a.div);
-        settle();
-        if (v < ktier) {
-            pend_old = atomicAdd(&cnt[(uint32_t)v >> 1], 1u << (((uint32_t)v & 1u) << 4));
-            pend_v = (uint32_t)v;
-        } else if (v < a.k) {
-            __hip_atomic_fetch_add(a.deg + v, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        xs ^= ((u << 32) + v) * (2 * i + 1);
-    };
-
-    // claimed (wave-uniform): edges handed out so far, the first 64 at the
-    // start and one more per finished edge (those past tot stay idle)
-    uint32_t li = lane, claimed = kWave, next_bar = kWave + kStreamRoundClaims;
-    uint64_t bars = 0;
-    auto round_edge = [&]() {
-        if (claimed >= next_bar) {
-            settle();
-            lds_barrier();
-            bars++;
-            next_bar += kStreamRoundClaims;
-        }
-    };
-    R r = rbase + 2 * (R)li;
-    if (tot >= kWave) {
-        while (claimed + kWave <= tot) {  // every lane holds a live edge
-            r = hash(r);
-            const bool fin = !(r & 1);
-            const uint64_t dm = __ballot(fin);
-            if (fin) {
-                finish(li, r);
-                li = claimed + lane_rank(dm);
-                r = rbase + 2 * (R)li;
-            }
-            claimed += (uint32_t)__popcll(dm);
-            round_edge();
-        }
-    }
-    bool active = li < tot;
-    uint64_t live = __ballot(active);
-    while (live) {
-        r = hash(r);
-        const bool done = active && !(r & 1);
-        const uint64_t dm = __ballot(done);
-        if (done) {
-            finish(li, r);
-            li = claimed + lane_rank(dm);
-            active = li < tot;
-            r = rbase + 2 * (R)li;
-        }
-        claimed += (uint32_t)__popcll(dm);
-        round_edge();
-        live = __ballot(active);
-    }
-    settle();
-    for (; bars < a.rounds; bars++) lds_barrier();
-
-    if (a.cs) {
-        for (int o = 32; o > 0; o >>= 1) xs ^= __shfl_xor(xs, o);
-        if (lane == 0 && xs) __hip_atomic_fetch_xor(a.cs, xs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    for (uint32_t w = threadIdx.x; w < kPackedNodes / 2; w += kStreamBlock) {
-        const uint32_t c = cnt[w];
-        const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
-        if (lo && 2 * w < ktier)
-            __hip_atomic_fetch_add(a.deg + 2 * w, (uint64_t)lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (hi && 2 * w + 1 < ktier)
-            __hip_atomic_fetch_add(a.deg + 2 * w + 1, (uint64_t)hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
 // ------------------------------------------------------------ host side
 
 static thread_local int g_last_hip = 0;
@@ -745,100 +541,11 @@ static int launch_first_endpoints(T *deg, uint64_t n, uint64_t begin, uint64_t c
     return hip_check(hipGetLastError());
 }
 
-// One streaming launch per slice of at most max_waves << wave_log2 edges, so
-// no wave takes more than 2^wave_log2 of them (launches accumulate).
-template <class L>
-static int launch_stream_slices(const StreamArgs &a0, uint64_t max_waves, unsigned wave_log2, L launch)
-{
-    const uint64_t slice = max_waves << wave_log2;
-    for (uint64_t off = 0; off < a0.count; off += slice) {
-        StreamArgs a = a0;
-        a.begin = a0.begin + off;
-        a.count = std::min(slice, a0.count - off);
-        const int rc = launch(a);
-        if (rc) return rc;
-    }
-    return BA_OK;
-}
+}  // namespace ba
 
-// 16K tier: a block's LDS counts stay below 16 * 2^27 = 2^31.
-template <bool N>
-static int launch_stream_one(const StreamArgs &a0, hipStream_t st)
-{
-    uint32_t grid0 = 0;
-    int rc = persistent_grid(k_stream<N>, kStreamBlock, &grid0);
-    if (rc) return rc;
-    const uint64_t max_waves = (uint64_t)grid0 * kStreamWaves;
-    return launch_stream_slices(a0, max_waves, 27, [&](StreamArgs a) {
-        uint64_t per_wave = (a.count + max_waves - 1) / max_waves;
-        per_wave = (per_wave + kWave - 1) / kWave * kWave;
-        if (per_wave < 4 * kWave) per_wave = 4 * kWave;
-        a.per_wave = per_wave;
-        const uint64_t waves = (a.count + per_wave - 1) / per_wave;
-        const uint32_t grid = (uint32_t)((waves + kStreamWaves - 1) / kStreamWaves);
-        return launch_timed(BA_KT_STREAM, st,
-                            [&] { hipLaunchKernelGGL((k_stream<N>), dim3(grid), dim3(kStreamBlock), 0, st, a); });
-    });
-}
+#include "ba_stream.h"
 
-// 64K tier: a wave's share stays below 2^30 edges (32-bit claim counters).
-template <bool N>
-static int launch_stream_packed(const StreamArgs &a0, hipStream_t st)
-{
-    uint32_t grid0 = 0;
-    int rc = persistent_grid(k_stream_packed<N>, kStreamBlock, &grid0);
-    if (rc) return rc;
-    const uint64_t max_waves = (uint64_t)grid0 * kStreamWaves;
-    return launch_stream_slices(a0, max_waves, 30, [&](StreamArgs a) {
-        uint64_t per_wave = (a.count + max_waves - 1) / max_waves;
-        per_wave = (per_wave + kWave - 1) / kWave * kWave;
-        if (per_wave < kStreamRoundClaims) per_wave = kStreamRoundClaims;
-        a.per_wave = per_wave;
-        a.rounds = per_wave / kStreamRoundClaims;  // no wave takes more barriers in its loop
-        const uint64_t waves = (a.count + per_wave - 1) / per_wave;
-        const uint32_t grid = (uint32_t)((waves + kStreamWaves - 1) / kStreamWaves);
-        a.klds = (uint32_t)(a.k < kPackedNodes ? a.k : kPackedNodes);
-        return launch_timed(BA_KT_STREAM, st,
-                            [&] { hipLaunchKernelGGL((k_stream_packed<N>), dim3(grid), dim3(kStreamBlock), 0, st, a); });
-    });
-}
-
-// LDS counter tier of the streaming launches (BA_TIER_*).
-static std::atomic<int> g_stream_tier{BA_TIER_AUTO};
-
-// BA_TIER_AUTO.  A target lands on node v with probability close to
-// 1 / (2 sqrt(v n)), so about (sqrt(min(k, 65536)) - 128) / sqrt(n) of all
-// targets fall in [16384, min(k, 65536)): the global atomics the 64K tier
-// saves.  Its one block per compute unit and round barriers cost about a
-// quarter more time per edge (measured on MI355X), which the saved atomics
-// outweigh once that share passes about 1.8%.
-static int stream_tier(uint64_t n, uint64_t k)
-{
-    const int t = g_stream_tier.load(std::memory_order_relaxed);
-    if (t != BA_TIER_AUTO) return t;
-    if (k <= kLdsNodes) return BA_TIER_16K;
-    const double share = (std::sqrt((double)std::min<uint64_t>(k, kPackedNodes)) - 128.0) / std::sqrt((double)n);
-    return share > 0.018 ? BA_TIER_64K : BA_TIER_16K;
-}
-
-static int launch_stream(uint64_t n, uint64_t begin, uint64_t count, uint32_t d, uint64_t seed, uint64_t k,
-                         uint64_t *deg, uint64_t *cs, hipStream_t st)
-{
-    if (count == 0) return BA_OK;
-    StreamArgs a{};
-    a.key = make_hash_key(seed);
-    a.div = make_divider(d);
-    a.begin = begin;
-    a.count = count;
-    a.k = k;
-    a.klds = (uint32_t)(k < kLdsNodes ? k : kLdsNodes);
-    a.deg = deg;
-    a.cs = cs;
-    const bool narrow = 2 * (begin + count) <= ((uint64_t)1 << 32);
-    if (stream_tier(n, k) == BA_TIER_64K) return narrow ? launch_stream_packed<true>(a, st) : launch_stream_packed<false>(a, st);
-    return narrow ? launch_stream_one<true>(a, st) : launch_stream_one<false>(a, st);
-}
-
+namespace ba {
 
 // ---------------------------------------------------------------------------
 // Batched generation: device table layout, upload, launch, tile-shape tuning.
