@@ -100,16 +100,16 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream(StreamArgs a)
 // A 16-bit counter could wrap, so the block synchronises in rounds.  Chains
 // in flight carry across a round boundary; a wave takes its next barrier as
 // soon as it has handed out kStreamRoundClaims more edges, so it finishes at
-// most kStreamRoundClaims + 63 edges between two barriers, and the block at
-// most 16 * 2047 = 32752.  A counter below 0x8000 at a barrier therefore
+// most kStreamRoundClaims + 127 edges between two barriers (two chains per
+// lane), and the block at most 16 * 2047 = 32752.  A counter below 0x8000 at a barrier therefore
 // stays at or below 0xFFFF until the next one; the lane whose increment takes
 // it from 0x7FFF to 0x8000 moves those 32768 counts to the global degree
 // before its wave's next barrier.  Every counter is below 0x8000 again at
 // each barrier, and the counts are exact.  Waves that run out of edges early
 // take their remaining barriers at the end, so all take a.rounds of them.
 constexpr uint32_t kPackedNodes = 65536;
-constexpr uint32_t kStreamRoundClaims = 1984;
-static_assert(kStreamWaves * (kStreamRoundClaims + kWave - 1) <= 0x8000, "a round must not wrap a 16-bit counter");
+constexpr uint32_t kStreamRoundClaims = 1920;
+static_assert(kStreamWaves * (kStreamRoundClaims + 2 * kWave - 1) <= 0x8000, "a round must not wrap a 16-bit counter");
 
 template <bool NARROW>
 __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
@@ -129,11 +129,11 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
     uint64_t xs = 0;
 
     // The value a lane's last LDS increment returned is examined at its next
-    // finished edge (or before its wave's next barrier), so the wave does not
-    // wait for the atomic's result right after issuing it.
+    // finished edge of the same chain (or before its wave's next barrier),
+    // so the wave does not wait for the atomic's result right after issuing
+    // it.
     constexpr uint32_t kNone = 0xFFFFFFFFu;
-    uint32_t pend_old = 0, pend_v = kNone;
-    auto settle = [&]() {
+    auto settle = [&](uint32_t &pend_old, uint32_t &pend_v) {
         if (pend_v != kNone) {
             const uint32_t sh = (pend_v & 1u) << 4;
             if (((pend_old >> sh) & 0xFFFFu) == 0x7FFFu) {
@@ -147,11 +147,11 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
         if constexpr (NARROW) return hash_narrow(r, a.key);
         else return hash_wide(r, a.key);
     };
-    auto finish = [&](uint32_t li, R r) {
+    auto finish = [&](uint32_t li, R r, uint32_t &pend_old, uint32_t &pend_v) {
         const uint64_t i = ibase + li;
         const uint64_t v = NARROW ? (uint64_t)div32((uint32_t)(r >> 1), a.div) : div64(r >> 1, a.div);
         const uint64_t u = NARROW ? (uint64_t)div32((uint32_t)i, a.div) : div64(i, a.div);
-        settle();
+        settle(pend_old, pend_v);
         if (v < ktier) {
             pend_old = atomicAdd(&cnt[(uint32_t)v >> 1], 1u << (((uint32_t)v & 1u) << 4));
             pend_v = (uint32_t)v;
@@ -161,50 +161,72 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
         xs ^= ((u << 32) + v) * (2 * i + 1);
     };
 
-    // claimed (wave-uniform): edges handed out so far, the first 64 at the
-    // start and one more per finished edge (those past tot stay idle)
-    uint32_t li = lane, claimed = kWave, next_bar = kWave + kStreamRoundClaims;
+    // Every lane runs two chains (A and B): their hash evaluations are
+    // independent, which hides latency at the one block per compute unit
+    // this tier allows.  claimed (wave-uniform): edges handed out so far,
+    // the first 128 at the start and one more per finished edge (those past
+    // tot stay idle).  Up to 128 edges finish per step, so a wave finishes
+    // at most kStreamRoundClaims + 127 edges between two barriers.
+    uint32_t pa_old = 0, pa_v = kNone, pb_old = 0, pb_v = kNone;
+    uint32_t la = lane, lb = lane + kWave, claimed = 2 * kWave, next_bar = 2 * kWave + kStreamRoundClaims;
     uint64_t bars = 0;
     auto round_edge = [&]() {
         if (claimed >= next_bar) {
-            settle();
+            settle(pa_old, pa_v);
+            settle(pb_old, pb_v);
             lds_barrier();
             bars++;
             next_bar += kStreamRoundClaims;
         }
     };
-    R r = rbase + 2 * (R)li;
-    if (tot >= kWave) {
-        while (claimed + kWave <= tot) {  // every lane holds a live edge
-            r = hash(r);
-            const bool fin = !(r & 1);
-            const uint64_t dm = __ballot(fin);
-            if (fin) {
-                finish(li, r);
-                li = claimed + lane_rank(dm);
-                r = rbase + 2 * (R)li;
+    R ra = rbase + 2 * (R)la, rb = rbase + 2 * (R)lb;
+    if (tot >= 2 * kWave) {
+        while (claimed + 2 * kWave <= tot) {  // every lane holds two live edges
+            ra = hash(ra);
+            rb = hash(rb);
+            const bool fa = !(ra & 1), fb = !(rb & 1);
+            const uint64_t ma = __ballot(fa), mb = __ballot(fb);
+            if (fa) {
+                finish(la, ra, pa_old, pa_v);
+                la = claimed + lane_rank(ma);
+                ra = rbase + 2 * (R)la;
             }
-            claimed += (uint32_t)__popcll(dm);
+            claimed += (uint32_t)__popcll(ma);
+            if (fb) {
+                finish(lb, rb, pb_old, pb_v);
+                lb = claimed + lane_rank(mb);
+                rb = rbase + 2 * (R)lb;
+            }
+            claimed += (uint32_t)__popcll(mb);
             round_edge();
         }
     }
-    bool active = li < tot;
-    uint64_t live = __ballot(active);
+    bool aa = la < tot, ab = lb < tot;
+    uint64_t live = __ballot(aa || ab);
     while (live) {
-        r = hash(r);
-        const bool done = active && !(r & 1);
-        const uint64_t dm = __ballot(done);
-        if (done) {
-            finish(li, r);
-            li = claimed + lane_rank(dm);
-            active = li < tot;
-            r = rbase + 2 * (R)li;
+        ra = hash(ra);
+        rb = hash(rb);
+        const bool fa = aa && !(ra & 1), fb = ab && !(rb & 1);
+        const uint64_t ma = __ballot(fa), mb = __ballot(fb);
+        if (fa) {
+            finish(la, ra, pa_old, pa_v);
+            la = claimed + lane_rank(ma);
+            aa = la < tot;
+            ra = rbase + 2 * (R)la;
         }
-        claimed += (uint32_t)__popcll(dm);
+        claimed += (uint32_t)__popcll(ma);
+        if (fb) {
+            finish(lb, rb, pb_old, pb_v);
+            lb = claimed + lane_rank(mb);
+            ab = lb < tot;
+            rb = rbase + 2 * (R)lb;
+        }
+        claimed += (uint32_t)__popcll(mb);
         round_edge();
-        live = __ballot(active);
+        live = __ballot(aa || ab);
     }
-    settle();
+    settle(pa_old, pa_v);
+    settle(pb_old, pb_v);
     for (; bars < a.rounds; bars++) lds_barrier();
 
     if (a.cs) {
