@@ -43,43 +43,34 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream(StreamArgs a)
     for (uint32_t v = threadIdx.x; v < a.klds; v += kStreamBlock) cnt[v] = 0;
     __syncthreads();
 
+    using R = typename std::conditional<NARROW, uint32_t, uint64_t>::type;
     const uint32_t lane = __lane_id();
-    const uint64_t gw = (uint64_t)blockIdx.x * kStreamWaves + threadIdx.x / kWave;
+    // wave-uniform (readfirstlane): keeps the loop control scalar
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const uint64_t gw = (uint64_t)blockIdx.x * kStreamWaves + wv;
     const uint64_t w0 = gw * a.per_wave;
     uint64_t xs = 0;
     if (w0 < a.count) {
-        const uint64_t wn = min(a.per_wave, a.count - w0);
+        // per_wave < 2^32: the host splits larger launches
+        const uint32_t tn = (uint32_t)min(a.per_wave, a.count - w0);
         const uint64_t ibase = a.begin + w0;
-        uint64_t li = lane;
-        bool active = li < wn;
-        uint64_t next = kWave, remaining = wn;
-        uint64_t r = 2 * (ibase + li) + 1;
-        while (remaining) {
-            if constexpr (NARROW)
-                r = hash_narrow((uint32_t)r, a.key);
-            else
-                r = hash_wide(r, a.key);
-            const bool done = active && !(r & 1u);
-            const uint64_t dm = __ballot(done);
-            if (done) {
+        chain_tile_visit(
+            tn, lane, (R)(2 * ibase + 1),
+            [&](R r) -> R {
+                if constexpr (NARROW) return hash_narrow(r, a.key);
+                else return hash_wide(r, a.key);
+            },
+            [](R r) { return !((uint32_t)r & 1u); },
+            [&](uint32_t li, R r) {
                 const uint64_t i = ibase + li;
-                const uint64_t v = NARROW ? (uint64_t)div32((uint32_t)(r >> 1), a.div)
-                                          : div64(r >> 1, a.div);
+                const uint64_t v = NARROW ? (uint64_t)div32((uint32_t)(r >> 1), a.div) : div64(r >> 1, a.div);
                 const uint64_t u = NARROW ? (uint64_t)div32((uint32_t)i, a.div) : div64(i, a.div);
                 if (v < a.klds)
                     atomicAdd(&cnt[v], 1u);
                 else if (v < a.k)
-                    __hip_atomic_fetch_add(a.deg + v, (uint64_t)1, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_add(a.deg + v, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 xs ^= ((u << 32) + v) * (2 * i + 1);
-                li = next + lane_rank(dm);
-                active = li < wn;
-                r = 2 * (ibase + li) + 1;
-            }
-            const uint32_t nd = (uint32_t)__popcll(dm);
-            next += nd;
-            remaining -= nd;
-        }
+            });
     }
     if (a.cs) {
         for (int o = 32; o > 0; o >>= 1) xs ^= __shfl_xor(xs, o);
@@ -119,7 +110,9 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
     __syncthreads();
     using R = typename std::conditional<NARROW, uint32_t, uint64_t>::type;
     const uint32_t lane = __lane_id();
-    const uint64_t gw = (uint64_t)blockIdx.x * kStreamWaves + threadIdx.x / kWave;
+    // wave-uniform (readfirstlane): keeps the loop control scalar
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const uint64_t gw = (uint64_t)blockIdx.x * kStreamWaves + wv;
     const uint64_t w0 = gw * a.per_wave;
     // edges of this wave (per_wave < 2^32: the host splits larger launches)
     const uint32_t tot = w0 < a.count ? (uint32_t)min(a.per_wave, a.count - w0) : 0u;
@@ -184,7 +177,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
         while (claimed + 2 * kWave <= tot) {  // every lane holds two live edges
             ra = hash(ra);
             rb = hash(rb);
-            const bool fa = !(ra & 1), fb = !(rb & 1);
+            const bool fa = !((uint32_t)ra & 1u), fb = !((uint32_t)rb & 1u);
             const uint64_t ma = __ballot(fa), mb = __ballot(fb);
             if (fa) {
                 finish(la, ra, pa_old, pa_v);
@@ -206,7 +199,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
     while (live) {
         ra = hash(ra);
         rb = hash(rb);
-        const bool fa = aa && !(ra & 1), fb = ab && !(rb & 1);
+        const bool fa = aa && !((uint32_t)ra & 1u), fb = ab && !((uint32_t)rb & 1u);
         const uint64_t ma = __ballot(fa), mb = __ballot(fb);
         if (fa) {
             finish(la, ra, pa_old, pa_v);
