@@ -169,7 +169,7 @@ __device__ __forceinline__ void chain_tile_until(uint32_t *stage, uint32_t tn, u
 template <class R, class H, class O>
 __device__ __forceinline__ void chain_tile(uint32_t *stage, uint32_t tn, uint32_t lane, R rbase, H hash, O out)
 {
-    chain_tile_until(stage, tn, lane, rbase, hash, [](R r) { return !(r & 1); }, out);
+    chain_tile_until(stage, tn, lane, rbase, hash, [](R r) { return !((uint32_t)r & 1u); }, out);
 }
 
 // One chain step for every lane, then refill of the lanes that finished.
@@ -238,33 +238,21 @@ struct Gen64Args {
 __global__ __launch_bounds__(kGenBlock) void k_gen_u64(Gen64Args a)
 {
     const uint32_t lane = __lane_id();
-    const uint32_t wv = threadIdx.x / kWave;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform: scalar loops
     const uint64_t wstride = (uint64_t)gridDim.x * kGenWaves;
     for (uint64_t c = (uint64_t)blockIdx.x * kGenWaves + wv; c < a.nchunks; c += wstride) {
         const uint64_t off = c * kTile;
         const uint32_t tn = (uint32_t)min((uint64_t)kTile, a.count - off);
         const uint64_t ibase = a.begin + off;
-        uint32_t li = lane;
-        bool active = li < tn;
-        uint32_t next = kWave, remaining = tn;
-        uint64_t r = 2 * (ibase + li) + 1;
-        while (remaining) {
-            r = hash_wide(r, a.key);
-            const bool done = active && !(r & 1u);
-            const uint64_t dm = __ballot(done);
-            if (done) {
-                const uint64_t i = ibase + li;
-                uint64_t *o = a.edges + 2 * (off + li);
-                o[0] = div64(i, a.div);
+        uint64_t *out = a.edges + 2 * off;
+        chain_tile_visit(
+            tn, lane, 2 * ibase + 1, [&](uint64_t r) { return hash_wide(r, a.key); },
+            [](uint64_t r) { return !((uint32_t)r & 1u); },
+            [&](uint32_t li, uint64_t r) {
+                uint64_t *o = out + 2 * li;
+                o[0] = div64(ibase + li, a.div);
                 o[1] = div64(r >> 1, a.div);
-                li = next + lane_rank(dm);
-                active = li < tn;
-                r = 2 * (ibase + li) + 1;
-            }
-            const uint32_t nd = (uint32_t)__popcll(dm);
-            next += nd;
-            remaining -= nd;
-        }
+            });
     }
 }
 

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kGenBlock) void k_gen_model(ModelArgs a)
             return hash_bounded(r, b, a.key);
         }
     };
-    auto stop = [&](R r) { return r < P0 || !(r & 1); };
+    auto stop = [&](R r) { return r < P0 || !((uint32_t)r & 1u); };
     auto node = [&](R r) -> uint32_t { return r < P0 ? a.S[r] : (uint32_t)(a.n0 + divd((r - P0) >> 1)); };
 
     for (uint64_t tile = (uint64_t)blockIdx.x * kGenWaves + wv; tile < a.ntiles; tile += wstride) {
