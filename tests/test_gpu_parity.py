@@ -189,6 +189,39 @@ def test_streaming_degrees_of_two_very_heavy_nodes(_tier, tier, begin, d):
     assert (int(cs.item()) & M64) == rcs
 
 
+@pytest.mark.parametrize("tier", [ba.TIER_16K, ba.TIER_64K])
+def test_streaming_tiers_on_wide_positions_accumulate(_tier, tier):
+    """Both tiers on ranges with 64-bit positions (around 2^31 and 2^32 and
+    beyond), first_k = 10^5, so LDS counters, the 16-bit wrap moves and the
+    global atomics all run on the wide kernels."""
+    n, d, seed, k = 1 << 30, 16, 9, 100000
+    ba.degrees_tier(tier)
+    deg = torch.zeros(k, dtype=torch.int64, device="cuda")
+    cs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ref = np.zeros(k, dtype=np.uint64)
+    rcs = 0
+    for b, c in [((1 << 31) - 70000, 140000), ((1 << 32) - 100000, 300000), (3 << 32, 250000)]:
+        _say("tier range", tier, b, c)
+        ba.degrees_range(n, d, seed, b, c, k, deg, cs)
+        ref, rcs, _ = oracle.stream(d, seed, b, c, k, ref, rcs)
+    torch.cuda.synchronize()
+    assert np.array_equal(_u64(deg), ref)
+    assert (int(cs.item()) & M64) == rcs
+
+
+@pytest.mark.parametrize("tier", [ba.TIER_AUTO, ba.TIER_16K, ba.TIER_64K])
+def test_streaming_checksum_alone(_tier, tier):
+    """first_k = 0: no degree is counted, the checksum is still every edge's."""
+    n, d, seed = 50000, 7, 13
+    _say("checksum only", tier)
+    ba.degrees_tier(tier)
+    deg, cs = ba.degrees(n, d, seed, 0)
+    torch.cuda.synchronize()
+    assert deg.numel() == 0
+    E, _ = oracle.bb_generate(n, d, seed)
+    assert cs == oracle.checksum_E(E)
+
+
 def test_degrees_through_the_stream_ordered_allocator():
     # ba_generate without a workspace takes one from hipMallocAsync
     n, d, seed = 70000, 6, 21
