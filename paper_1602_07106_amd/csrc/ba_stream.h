@@ -92,12 +92,13 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream(StreamArgs a)
 // in flight carry across a round boundary; a wave takes its next barrier as
 // soon as it has handed out kStreamRoundClaims more edges, so it finishes at
 // most kStreamRoundClaims + 127 edges between two barriers (two chains per
-// lane), and the block at most 16 * 2047 = 32752.  A counter below 0x8000 at a barrier therefore
-// stays at or below 0xFFFF until the next one; the lane whose increment takes
-// it from 0x7FFF to 0x8000 moves those 32768 counts to the global degree
-// before its wave's next barrier.  Every counter is below 0x8000 again at
-// each barrier, and the counts are exact.  Waves that run out of edges early
-// take their remaining barriers at the end, so all take a.rounds of them.
+// lane), and the block at most 16 * 2047 = 32752.  A counter below 0x8000 at
+// a barrier therefore stays at or below 0xFFFF until the next one; the lane
+// whose increment takes it from 0x7FFF to 0x8000 moves those 32768 counts to
+// the global degree before its wave's next barrier.  Every counter is below
+// 0x8000 again at each barrier, and the counts are exact.  Waves that run
+// out of edges early take their remaining barriers at the end, so all take
+// a.rounds of them.
 constexpr uint32_t kPackedNodes = 65536;
 constexpr uint32_t kStreamRoundClaims = 1920;
 static_assert(kStreamWaves * (kStreamRoundClaims + 2 * kWave - 1) <= 0x8000, "a round must not wrap a 16-bit counter");
@@ -303,9 +304,10 @@ static std::atomic<int> g_stream_tier{BA_TIER_AUTO};
 // BA_TIER_AUTO.  A target lands on node v with probability close to
 // 1 / (2 sqrt(v n)), so about (sqrt(min(k, 65536)) - 128) / sqrt(n) of all
 // targets fall in [16384, min(k, 65536)): the global atomics the 64K tier
-// saves.  Its one block per compute unit and round barriers cost about a
-// quarter more time per edge (measured on MI355X), which the saved atomics
-// outweigh once that share passes about 1.8%.
+// saves.  Its one block per compute unit and round barriers cost up to a
+// third more time per edge (measured on MI355X: nothing at n = 2^26 with
+// 32-bit positions, 35% at n = 2^30 with 64-bit ones), which the saved
+// atomics outweigh once that share passes about 1.8%.
 static int stream_tier(uint64_t n, uint64_t k)
 {
     const int t = g_stream_tier.load(std::memory_order_relaxed);
