@@ -33,7 +33,7 @@ N, D, SEED = 1 << 26, 16, 7
 M = N * D
 HBM_PEAK = 8.0e12                          # MI355X HBM3E, bytes/s
 VALU_PEAK = 256 * 64 * 2.4e9               # 32-bit lane-cycles/s: 256 CUs x 64 lanes x 2.4 GHz
-# Algorithmic work per edge (derivations in the design doc):
+# Algorithmic work per edge:
 #  chain kernel: hash evaluations per edge of this graph (2,147,478,402 over
 #  its 2^30 edges, counted by the CPU oracle) x VALU issue cycles of one
 #  narrow (r < 2^32) evaluation, plus fixed cycles per edge; it writes the
@@ -419,7 +419,8 @@ def main() -> int:
         return copy_calibration(args.copy_calibration)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the generator here has no multi-GPU path "
-              "(DESIGN.md describes how it would shard); use --gpus 1", file=sys.stderr)
+              "(GPUs would take contiguous edge-ID ranges, with no exchange but one reduction "
+              "of the degree counts); use --gpus 1", file=sys.stderr)
         return 2
     if args.workload == "batch":
         return bench_batch(args)
