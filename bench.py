@@ -402,15 +402,101 @@ def bench_stream(args) -> int:
     return 0
 
 
+# Generalized-model workload: n=2^26, d=16, seed=7 with a seed graph of
+# n0=100 nodes and m0=1000 edges (workloads.seed_graph) in front of the new
+# edges; the four variants of the hash (fmix, the paper's CRC) and the
+# draw bound (self-loops allowed or not).
+MODEL = (1 << 26, 16, 7, 100, 1000)
+
+
+def bench_model(args) -> int:
+    import numpy as np
+    import torch
+
+    import paper_1602_07106_amd as ba
+    import workloads
+
+    n, d, seed, n0, m0 = MODEL
+    m = (n - n0) * d
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    S_host = workloads.seed_graph(n0, m0)
+    S = torch.from_numpy(S_host.astype(np.int32)).to(dev)
+    out = torch.empty((m, 2), dtype=torch.int32, device=dev)
+    variants = {}
+    for h in ("fmix", "crc"):
+        for nl in (False, True):
+            def f():
+                ba.generate_model(n, d, seed, n0=n0, seed_edges=S, no_self_loops=nl, hash=h, out=out)
+
+            for _ in range(args.warmup):
+                f()
+            torch.cuda.synchronize()
+            ba.kernel_timing(True)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                f()
+            e1.record()
+            torch.cuda.synchronize()
+            kt = ba.kernel_timing_read()
+            ba.kernel_timing(False)
+            ms = e0.elapsed_time(e1) / args.steps
+            g_ms, g_n = kt["gen"]
+            name = h + (", no self-loops" if nl else "")
+            variants[name] = {"edges_per_s": m / (ms / 1e3), "ms_per_step": round(ms, 4),
+                              "kernel_ms": round(g_ms / g_n, 4)}
+    main = variants["fmix"]
+    t = main["kernel_ms"] / 1e3
+    hashes = m * (2.0 - 1.77 / m ** 0.5)
+    cyc = hashes * CYCLES_PER_HASH + m * CYCLES_PER_EDGE
+    byts = 8.0 * m
+    line = {
+        "metric": "edges/s, generalized model (100-node, 1000-edge seed graph) at n=2^26, d=16",
+        "value": main["edges_per_s"],
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded seed graph from workloads.seed_graph; the generator is the workload)",
+        "config": {"workload": "generalized model: seed graph n0=100, m0=1000, then n=2^26, d=16, seed=7; "
+                               "uint32 edge pairs of the new edges", "edges": m, "variants": variants},
+        "roofline": {"bound": "hbm", "achieved": round(byts / t / 1e9, 2), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": round(byts / t / HBM_PEAK, 4), "traffic": None,
+                     "kernel": "k_gen_model (fmix, 32-bit positions)", "kernel_ms": main["kernel_ms"],
+                     "alg_bytes_per_launch": byts, "alu_frac": round(cyc / t / VALU_PEAK, 4)},
+    }
+    if not args.no_cpu_baseline:
+        import time as _t
+
+        import oracle
+
+        c = 1 << 26
+        t0 = _t.perf_counter()
+        oracle.model_edges_range(n0, m0, S_host, d, seed, 0, 0, c)
+        dt = _t.perf_counter() - t0
+        line["cpu_baseline"] = {"value": c / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                                "sample": "first 2^26 new edges, fmix hash, per-edge chains, %.1f s" % dt}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["graph", "batch", "served", "stream"], default="graph",
+    ap.add_argument("--workload", choices=["graph", "batch", "served", "stream", "model"], default="graph",
                     help="graph: the n=2^26, d=16 graph with degrees (default); batch: 4096 graphs; "
                          "served: a 4000-request trace through the continuous-batching server; "
-                         "stream: streamed first-10^5 degrees at n=2^30, d=64")
+                         "stream: streamed first-10^5 degrees at n=2^30, d=64; "
+                         "model: the generalized model (seed graph, no-self-loop draws, CRC hash)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers (reference for HBM counters)")
@@ -426,6 +512,8 @@ def main() -> int:
         return bench_batch(args)
     if args.workload == "served":
         return bench_served(args)
+    if args.workload == "model":
+        return bench_model(args)
     if args.workload == "stream":
         return bench_stream(args)
 

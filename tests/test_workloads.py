@@ -43,3 +43,12 @@ def test_served_trace_shape():
     # offered load: mean edges per request x rate, about 5e11 edges/s
     offered = float((n.astype(np.float64) * d).mean()) * rate
     assert 3e11 < offered < 8e11
+
+
+def test_seed_graph_is_seeded_and_in_range():
+    a = workloads.seed_graph(100, 1000)
+    b = workloads.seed_graph(100, 1000)
+    assert a.dtype == np.uint32 and a.size == 2000
+    assert np.array_equal(a, b)
+    assert a.max() < 100 and len(np.unique(a)) == 100
+    assert not np.array_equal(a, workloads.seed_graph(100, 1000, seed=1))

@@ -54,3 +54,13 @@ def served_trace(count: int = 4000, rate: float = 2000.0, seed: int = SERVED_SEE
     first_k = np.where(kind == 1, np.minimum(n, 100000), 0).astype(np.uint64)
     return {"arrival_s": arrival, "n": n, "d": d, "seed": np.arange(count, dtype=np.uint64), "kind": kind,
             "first_k": first_k}
+
+
+SEED_GRAPH_SEED = 0x5EED6
+
+def seed_graph(n0: int = 100, m0: int = 1000, seed: int = SEED_GRAPH_SEED):
+    """The seed graph of the generalized-model workload: m0 edges between
+    nodes 0..n0-1, both endpoints uniform (a random multigraph, loops
+    allowed), as the 2*m0 node IDs of positions 0..2*m0-1 (uint32)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(0, n0, size=2 * m0).astype(np.uint32)
