@@ -338,6 +338,16 @@ int ba_last_hip_error(void);
  */
 int ba_host_divide(uint32_t d, const uint64_t *x, uint64_t *q, uint64_t count);
 
+/*
+ * Host-side self-test of the exact remainder x mod b (1 <= b < 2^32) that the
+ * CRC-hash kernels use on 32-bit positions for the paper's hash mod x: two
+ * quotient estimates in double precision, each followed by one exact
+ * correction.  Writes r[j] = x[j] mod b[j] for count host values, computed
+ * that way on the host.  Returns BA_OK, or BA_EINVAL for a NULL array with
+ * count > 0 or any b[j] = 0.
+ */
+int ba_host_mod64(const uint64_t *x, const uint32_t *b, uint32_t *r, uint64_t count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -79,6 +79,7 @@ _SIGS = {
     "ba_strerror": (ctypes.c_char_p, [_int]),
     "ba_last_hip_error": (_int, []),
     "ba_host_divide": (_int, [_u32, _p, _p, _u64]),
+    "ba_host_mod64": (_int, [_p, _p, _p, _u64]),
     "ba_kernel_timing": (_int, [_int]),
     "ba_kernel_timing_read": (_int, [_p, _p]),
     "ba_batch_workspace_bytes": (_u64, [_u32]),

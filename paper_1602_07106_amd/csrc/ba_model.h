@@ -56,6 +56,39 @@ __host__ __device__ __forceinline__ uint32_t crc32c_u64(const Tab &t, uint32_t c
            t[3][(v >> 32) & 0xFF] ^ t[2][(v >> 40) & 0xFF] ^ t[1][(v >> 48) & 0xFF] ^ t[0][v >> 56];
 }
 
+// x mod b for 1 <= b < 2^32, exact; there is no 64-by-32-bit division
+// instruction.  Two steps, each with a quotient estimate in double precision:
+// r1 = hi mod b, then (r1 * 2^32 + lo) mod b, whose quotient is below 2^32.
+// With y within 2^-48 of 1/b (a 2^-23 seed refined twice by Newton's
+// iteration), the estimate num * y is within 2^-17 of num / b: num converts
+// exactly below 2^53, and above it b > num / 2^32 > 2^21 bounds the
+// conversion's share of the error by 2^-21.  The truncated (and clamped)
+// estimate is therefore q - 1, q or q + 1, and one signed correction of
+// num - q_est * b gives the remainder.
+__host__ __device__ __forceinline__ uint32_t mod_u64_u32(uint64_t x, uint32_t b)
+{
+    const double bd = (double)b;
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = (double)__builtin_amdgcn_rcpf((float)b);
+#else
+    double y = (double)(1.0f / (float)b);
+#endif
+    y = fma(fma(-bd, y, 1.0), y, y);
+    y = fma(fma(-bd, y, 1.0), y, y);
+    auto reduce = [&](uint64_t num) -> uint32_t {  // num < b * 2^32
+        const double qd = (double)num * y;
+        const uint32_t q = qd >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)qd;
+        int64_t r = (int64_t)(num - (uint64_t)q * b);
+        if (r < 0)
+            r += b;
+        else if (r >= (int64_t)b)
+            r -= b;
+        return (uint32_t)r;
+    };
+    const uint32_t r1 = reduce(x >> 32);
+    return reduce(((uint64_t)r1 << 32) | (uint32_t)x);
+}
+
 enum : uint32_t { kModelNoLoops = 1, kModelCrc = 2 };
 
 struct ModelArgs {
@@ -102,7 +135,9 @@ __global__ __launch_bounds__(kGenBlock) void k_gen_model(ModelArgs a)
         const R b = bound(r);
         if constexpr (CRC) {
             const uint32_t c0 = crc32c_u64(crc_t, 0u, (uint64_t)r ^ a.key64);
-            return (R)(((((uint64_t)c0 << 32) + (uint64_t)(c0 ^ a.k1))) % (uint64_t)b);
+            const uint64_t h = ((uint64_t)c0 << 32) + (uint64_t)(c0 ^ a.k1);
+            if constexpr (NARROW) return mod_u64_u32(h, b);
+            else return h % b;
         } else if constexpr (NARROW) {
             return hash_narrow_bounded(r, b, a.key);
         } else {
@@ -138,3 +173,14 @@ __global__ __launch_bounds__(kGenBlock) void k_gen_model(ModelArgs a)
 }
 
 }  // namespace ba
+
+// Host self-test of mod_u64_u32 (the same algorithm the CRC kernels run,
+// with the reciprocal seed computed on the host): r[j] = x[j] mod b[j].
+extern "C" int ba_host_mod64(const uint64_t *x, const uint32_t *b, uint32_t *r, uint64_t count)
+{
+    if (count && (!x || !b || !r)) return BA_EINVAL;
+    for (uint64_t j = 0; j < count; j++)
+        if (b[j] == 0) return BA_EINVAL;
+    for (uint64_t j = 0; j < count; j++) r[j] = ba::mod_u64_u32(x[j], b[j]);
+    return BA_OK;
+}

@@ -74,6 +74,48 @@ def test_divide_rejects_zero_divisor():
     assert ba.lib().ba_host_divide(0, x.ctypes.data, x.ctypes.data, 1) == ba.BA_EINVAL
 
 
+def _host_mod(xs, bs):
+    x = np.ascontiguousarray(np.asarray(xs, dtype=np.uint64))
+    b = np.ascontiguousarray(np.asarray(bs, dtype=np.uint32))
+    r = np.zeros(x.size, dtype=np.uint32)
+    assert ba.lib().ba_host_mod64(x.ctypes.data, b.ctypes.data, r.ctypes.data, x.size) == 0
+    return [int(v) for v in r]
+
+
+def test_exact_remainder_on_boundaries():
+    """x mod b for the CRC hash (64-bit x, 32-bit b): divisors from 1 to
+    2^32 - 1 around the error-bound switch points (2^12, 2^21), dividends at
+    multiples of b, around 2^53 and up to 2^64 - 1."""
+    M = (1 << 64) - 1
+    divs = [1, 2, 3, 7, 4095, 4096, 4097, (1 << 21) - 1, 1 << 21, (1 << 21) + 1, 1000003, (1 << 31) - 1, 1 << 31,
+            (1 << 31) + 1, (1 << 32) - 3, (1 << 32) - 1]
+    xs, bs = [], []
+    for b in divs:
+        vals = {0, 1, b - 1, b, b + 1, (1 << 32) - 1, 1 << 32, (1 << 53) - 1, 1 << 53, (1 << 53) + 1, M - 1, M}
+        for k in [1, 2, (1 << 32) - 1, M // b, (M // b) - 1, ((1 << 53) // b)]:
+            for delta in (-1, 0, 1):
+                vals.add(k * b + delta)
+        for v in sorted(v for v in vals if 0 <= v <= M):
+            xs.append(v)
+            bs.append(b)
+    assert _host_mod(xs, bs) == [x % b for x, b in zip(xs, bs)]
+
+
+def test_exact_remainder_random():
+    rng = random.Random(11)
+    xs = [rng.getrandbits(rng.choice([32, 40, 53, 54, 63, 64])) for _ in range(200000)]
+    bs = [rng.randint(1, (1 << 32) - 1) if rng.random() < 0.6 else rng.randint(1, 1 << rng.randint(1, 31))
+          for _ in range(200000)]
+    assert _host_mod(xs, bs) == [x % b for x, b in zip(xs, bs)]
+
+
+def test_remainder_rejects_zero_divisor():
+    x = np.ones(2, dtype=np.uint64)
+    b = np.array([3, 0], dtype=np.uint32)
+    r = np.zeros(2, dtype=np.uint32)
+    assert ba.lib().ba_host_mod64(x.ctypes.data, b.ctypes.data, r.ctypes.data, 2) == ba.BA_EINVAL
+
+
 # Argument validation returns before any HIP call, so it runs without a GPU.
 # Pointer values below are never dereferenced.
 FAKE = 1 << 20
