@@ -144,7 +144,9 @@ int ba_degrees_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin,
  *   BA_TIER_AUTO : the default; BA_TIER_64K when first_k > 16384 and the
  *                  targets expected in [16384, min(first_k, 65536)), about
  *                  (sqrt(min(first_k, 65536)) - 128) / sqrt(n) of them,
- *                  exceed 1.8% (small n), else BA_TIER_16K.
+ *                  exceed 1.5% (all positions of the call below 2^32) or
+ *                  1.8% (64-bit positions), i.e. for small n; else
+ *                  BA_TIER_16K.
  *   BA_TIER_16K  : 32-bit LDS counters for nodes below 16384 (64 KiB per
  *                  block, two blocks per compute unit); every other target
  *                  below first_k is a global atomic.

@@ -36,7 +36,26 @@ struct StreamArgs {
     uint64_t *cs;       // nullable
 };
 
-template <bool NARROW>
+// floor(x / d) with the divider's kind fixed at compile time (the streaming
+// kernels divide on every finished edge; d is a power of two when POW2),
+// otherwise the same Granlund-Montgomery step as div32 / div64.
+template <bool POW2>
+__device__ __forceinline__ uint32_t sdiv32(uint32_t x, const Divider &v)
+{
+    if constexpr (POW2) return x >> v.shift;
+    const uint32_t t = mulhi32(x, v.m32);
+    return (t + ((x - t) >> 1)) >> v.shift;
+}
+
+template <bool POW2>
+__device__ __forceinline__ uint64_t sdiv64(uint64_t x, const Divider &v)
+{
+    if constexpr (POW2) return x >> v.shift;
+    const uint64_t t = mulhi64(x, v.m64);
+    return (t + ((x - t) >> 1)) >> v.shift;
+}
+
+template <bool NARROW, bool POW2>
 __global__ __launch_bounds__(kStreamBlock) void k_stream(StreamArgs a)
 {
     __shared__ uint32_t cnt[kLdsNodes];
@@ -63,8 +82,8 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream(StreamArgs a)
             [](R r) { return !((uint32_t)r & 1u); },
             [&](uint32_t li, R r) {
                 const uint64_t i = ibase + li;
-                const uint64_t v = NARROW ? (uint64_t)div32((uint32_t)(r >> 1), a.div) : div64(r >> 1, a.div);
-                const uint64_t u = NARROW ? (uint64_t)div32((uint32_t)i, a.div) : div64(i, a.div);
+                const uint64_t v = NARROW ? (uint64_t)sdiv32<POW2>((uint32_t)(r >> 1), a.div) : sdiv64<POW2>(r >> 1, a.div);
+                const uint64_t u = NARROW ? (uint64_t)sdiv32<POW2>((uint32_t)i, a.div) : sdiv64<POW2>(i, a.div);
                 if (v < a.klds)
                     atomicAdd(&cnt[v], 1u);
                 else if (v < a.k)
@@ -103,7 +122,7 @@ constexpr uint32_t kPackedNodes = 65536;
 constexpr uint32_t kStreamRoundClaims = 1920;
 static_assert(kStreamWaves * (kStreamRoundClaims + 2 * kWave - 1) <= 0x8000, "a round must not wrap a 16-bit counter");
 
-template <bool NARROW>
+template <bool NARROW, bool POW2>
 __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
 {
     __shared__ uint32_t cnt[kPackedNodes / 2];  // node v: word v >> 1, half v & 1
@@ -143,8 +162,8 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
     };
     auto finish = [&](uint32_t li, R r, uint32_t &pend_old, uint32_t &pend_v) {
         const uint64_t i = ibase + li;
-        const uint64_t v = NARROW ? (uint64_t)div32((uint32_t)(r >> 1), a.div) : div64(r >> 1, a.div);
-        const uint64_t u = NARROW ? (uint64_t)div32((uint32_t)i, a.div) : div64(i, a.div);
+        const uint64_t v = NARROW ? (uint64_t)sdiv32<POW2>((uint32_t)(r >> 1), a.div) : sdiv64<POW2>(r >> 1, a.div);
+        const uint64_t u = NARROW ? (uint64_t)sdiv32<POW2>((uint32_t)i, a.div) : sdiv64<POW2>(i, a.div);
         settle(pend_old, pend_v);
         if (v < ktier) {
             pend_old = atomicAdd(&cnt[(uint32_t)v >> 1], 1u << (((uint32_t)v & 1u) << 4));
@@ -257,11 +276,11 @@ static int launch_stream_slices(const StreamArgs &a0, uint64_t max_waves, unsign
 }
 
 // 16K tier: a block's LDS counts stay below 16 * 2^27 = 2^31.
-template <bool N>
+template <bool N, bool P>
 static int launch_stream_one(const StreamArgs &a0, hipStream_t st)
 {
     uint32_t grid0 = 0;
-    int rc = persistent_grid(k_stream<N>, kStreamBlock, &grid0);
+    int rc = persistent_grid(k_stream<N, P>, kStreamBlock, &grid0);
     if (rc) return rc;
     const uint64_t max_waves = (uint64_t)grid0 * kStreamWaves;
     return launch_stream_slices(a0, max_waves, 27, [&](StreamArgs a) {
@@ -272,16 +291,16 @@ static int launch_stream_one(const StreamArgs &a0, hipStream_t st)
         const uint64_t waves = (a.count + per_wave - 1) / per_wave;
         const uint32_t grid = (uint32_t)((waves + kStreamWaves - 1) / kStreamWaves);
         return launch_timed(BA_KT_STREAM, st,
-                            [&] { hipLaunchKernelGGL((k_stream<N>), dim3(grid), dim3(kStreamBlock), 0, st, a); });
+                            [&] { hipLaunchKernelGGL((k_stream<N, P>), dim3(grid), dim3(kStreamBlock), 0, st, a); });
     });
 }
 
 // 64K tier: a wave's share stays below 2^30 edges (32-bit claim counters).
-template <bool N>
+template <bool N, bool P>
 static int launch_stream_packed(const StreamArgs &a0, hipStream_t st)
 {
     uint32_t grid0 = 0;
-    int rc = persistent_grid(k_stream_packed<N>, kStreamBlock, &grid0);
+    int rc = persistent_grid(k_stream_packed<N, P>, kStreamBlock, &grid0);
     if (rc) return rc;
     const uint64_t max_waves = (uint64_t)grid0 * kStreamWaves;
     return launch_stream_slices(a0, max_waves, 30, [&](StreamArgs a) {
@@ -294,7 +313,7 @@ static int launch_stream_packed(const StreamArgs &a0, hipStream_t st)
         const uint32_t grid = (uint32_t)((waves + kStreamWaves - 1) / kStreamWaves);
         a.klds = (uint32_t)(a.k < kPackedNodes ? a.k : kPackedNodes);
         return launch_timed(BA_KT_STREAM, st,
-                            [&] { hipLaunchKernelGGL((k_stream_packed<N>), dim3(grid), dim3(kStreamBlock), 0, st, a); });
+                            [&] { hipLaunchKernelGGL((k_stream_packed<N, P>), dim3(grid), dim3(kStreamBlock), 0, st, a); });
     });
 }
 
@@ -304,17 +323,20 @@ static std::atomic<int> g_stream_tier{BA_TIER_AUTO};
 // BA_TIER_AUTO.  A target lands on node v with probability close to
 // 1 / (2 sqrt(v n)), so about (sqrt(min(k, 65536)) - 128) / sqrt(n) of all
 // targets fall in [16384, min(k, 65536)): the global atomics the 64K tier
-// saves.  Its one block per compute unit and round barriers cost up to a
-// third more time per edge (measured on MI355X: nothing at n = 2^26 with
-// 32-bit positions, 35% at n = 2^30 with 64-bit ones), which the saved
-// atomics outweigh once that share passes about 1.8%.
-static int stream_tier(uint64_t n, uint64_t k)
+// saves.  Those atomics cost more the smaller n is (the same first-k nodes
+// take more hits each), ~100 ps apiece at n = 2^26.  The 64K tier's one
+// block per compute unit and round barriers cost ~45% more compute per edge
+// with 32-bit positions and more with 64-bit ones.  Measured on MI355X
+// (first_k = 10^5, 32-bit positions) the tiers break even near n = 7e7, a
+// share of ~1.5%.  With 64-bit positions the 64K tier costs more compute
+// (~35% at n = 2^30) but the served mix still favours it above ~1.8%.
+static int stream_tier(uint64_t n, uint64_t k, bool narrow)
 {
     const int t = g_stream_tier.load(std::memory_order_relaxed);
     if (t != BA_TIER_AUTO) return t;
     if (k <= kLdsNodes) return BA_TIER_16K;
     const double share = (std::sqrt((double)std::min<uint64_t>(k, kPackedNodes)) - 128.0) / std::sqrt((double)n);
-    return share > 0.018 ? BA_TIER_64K : BA_TIER_16K;
+    return share > (narrow ? 0.015 : 0.018) ? BA_TIER_64K : BA_TIER_16K;
 }
 
 static int launch_stream(uint64_t n, uint64_t begin, uint64_t count, uint32_t d, uint64_t seed, uint64_t k,
@@ -331,8 +353,13 @@ static int launch_stream(uint64_t n, uint64_t begin, uint64_t count, uint32_t d,
     a.deg = deg;
     a.cs = cs;
     const bool narrow = 2 * (begin + count) <= ((uint64_t)1 << 32);
-    if (stream_tier(n, k) == BA_TIER_64K) return narrow ? launch_stream_packed<true>(a, st) : launch_stream_packed<false>(a, st);
-    return narrow ? launch_stream_one<true>(a, st) : launch_stream_one<false>(a, st);
+    const bool pow2 = a.div.pow2 != 0;
+    if (stream_tier(n, k, narrow) == BA_TIER_64K) {
+        if (narrow) return pow2 ? launch_stream_packed<true, true>(a, st) : launch_stream_packed<true, false>(a, st);
+        return pow2 ? launch_stream_packed<false, true>(a, st) : launch_stream_packed<false, false>(a, st);
+    }
+    if (narrow) return pow2 ? launch_stream_one<true, true>(a, st) : launch_stream_one<true, false>(a, st);
+    return pow2 ? launch_stream_one<false, true>(a, st) : launch_stream_one<false, false>(a, st);
 }
 
 }  // namespace ba

@@ -189,19 +189,21 @@ def test_streaming_degrees_of_two_very_heavy_nodes(_tier, tier, begin, d):
     assert (int(cs.item()) & M64) == rcs
 
 
+@pytest.mark.parametrize("d", [16, 12])
 @pytest.mark.parametrize("tier", [ba.TIER_16K, ba.TIER_64K])
-def test_streaming_tiers_on_wide_positions_accumulate(_tier, tier):
+def test_streaming_tiers_on_wide_positions_accumulate(_tier, tier, d):
     """Both tiers on ranges with 64-bit positions (around 2^31 and 2^32 and
     beyond), first_k = 10^5, so LDS counters, the 16-bit wrap moves and the
-    global atomics all run on the wide kernels."""
-    n, d, seed, k = 1 << 30, 16, 9, 100000
+    global atomics all run on the wide kernels, with d a power of two (shift)
+    and not (multiply-high division)."""
+    n, seed, k = 1 << 30, 9, 100000
     ba.degrees_tier(tier)
     deg = torch.zeros(k, dtype=torch.int64, device="cuda")
     cs = torch.zeros(1, dtype=torch.int64, device="cuda")
     ref = np.zeros(k, dtype=np.uint64)
     rcs = 0
-    for b, c in [((1 << 31) - 70000, 140000), ((1 << 32) - 100000, 300000), (3 << 32, 250000)]:
-        _say("tier range", tier, b, c)
+    for b, c in [((1 << 31) - 70000, 140000), ((1 << 32) - 100000, 300000), (n * d - 250000, 250000)]:
+        _say("tier range", tier, d, b, c)
         ba.degrees_range(n, d, seed, b, c, k, deg, cs)
         ref, rcs, _ = oracle.stream(d, seed, b, c, k, ref, rcs)
     torch.cuda.synchronize()
