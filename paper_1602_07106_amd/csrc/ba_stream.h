@@ -323,8 +323,8 @@ static std::atomic<int> g_stream_tier{BA_TIER_AUTO};
 // BA_TIER_AUTO.  A target lands on node v with probability close to
 // 1 / (2 sqrt(v n)), so about (sqrt(min(k, 65536)) - 128) / sqrt(n) of all
 // targets fall in [16384, min(k, 65536)): the global atomics the 64K tier
-// saves.  Those atomics cost more the smaller n is (the same first-k nodes
-// take more hits each), ~100 ps apiece at n = 2^26.  The 64K tier's one
+// saves.  Their cost per atomic grows with their share (~140 ps apiece
+// around n = 2^26, ~35 ps near n = 2^28, measured).  The 64K tier's one
 // block per compute unit and round barriers cost ~45% more compute per edge
 // with 32-bit positions and more with 64-bit ones.  Measured on MI355X
 // (first_k = 10^5, 32-bit positions) the tiers break even near n = 7e7, a
