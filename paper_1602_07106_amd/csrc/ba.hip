@@ -71,23 +71,41 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
 }
 
 
+// floor(x / d) with the divider's kind (a power of two or not) fixed at
+// compile time, so the flush loops carry no per-step branch on it.
+template <bool POW2>
+__device__ __forceinline__ uint32_t fdiv32(uint32_t x, const Divider &v)
+{
+    if constexpr (POW2) return x >> v.shift;
+    const uint32_t t = mulhi32(x, v.m32);
+    return (t + ((x - t) >> 1)) >> v.shift;
+}
+
+template <bool POW2>
+__device__ __forceinline__ uint64_t fdiv64(uint64_t x, const Divider &v)
+{
+    if constexpr (POW2) return x >> v.shift;
+    const uint64_t t = mulhi64(x, v.m64);
+    return (t + ((x - t) >> 1)) >> v.shift;
+}
+
 // Edge pair j, j+1 of a tile from the stage: u = floor(i/d) and v (the
 // stage holds floor(r/2) on the narrow path, v itself on the wide path).
-template <bool NARROW>
+template <bool NARROW, bool POW2>
 __device__ __forceinline__ void flush_pair(const GenArgs &a, const uint32_t *stage, uint64_t ibase, uint32_t j,
                                            uint32_t &u0, uint32_t &u1, uint32_t &v0, uint32_t &v1)
 {
     const uint2 s = *reinterpret_cast<const uint2 *>(stage + j);
     if constexpr (NARROW) {
         const uint32_t i0 = (uint32_t)ibase + j;
-        u0 = div32(i0, a.div);
-        u1 = div32(i0 + 1, a.div);
-        v0 = div32(s.x, a.div);
-        v1 = div32(s.y, a.div);
+        u0 = fdiv32<POW2>(i0, a.div);
+        u1 = fdiv32<POW2>(i0 + 1, a.div);
+        v0 = fdiv32<POW2>(s.x, a.div);
+        v1 = fdiv32<POW2>(s.y, a.div);
     } else {
         const uint64_t i0 = ibase + j;
-        u0 = (uint32_t)div64(i0, a.div);
-        u1 = (uint32_t)div64(i0 + 1, a.div);
+        u0 = (uint32_t)fdiv64<POW2>(i0, a.div);
+        u1 = (uint32_t)fdiv64<POW2>(i0 + 1, a.div);
         v0 = s.x;
         v1 = s.y;
     }
@@ -198,19 +216,49 @@ __global__ __launch_bounds__(kGenBlock) void k_gen_u32(GenArgs a)
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-        // Flush: two edges per lane per step, 16-byte stores.
+        // Flush: two edges per lane per step, 16-byte stores.  The divider's
+        // kind and whether the tile is full are uniform, so they select a
+        // loop instead of being tested in it; a full tile (all but a
+        // launch's last) needs no partial-pair checks.
         uint32_t *out = a.edges + 2 * off;
-        for (uint32_t j = 2 * lane; j < tn; j += 2 * kWave) {
-            uint32_t u0, u1, v0, v1;
-            flush_pair<NARROW>(a, stage, ibase, j, u0, u1, v0, v1);
-            store_pair<VEC16>(out, j, tn, u0, v0, u1, v1);
-            if constexpr (VLIST) {
-                // second endpoints alone, for the degree pipeline (8-byte aligned: j, off even)
-                if (j + 1 < tn)
-                    *reinterpret_cast<uint2 *>(a.vlist + off + j) = make_uint2(v0, v1);
-                else
-                    a.vlist[off + j] = v0;
+        auto flush = [&](auto pow2, auto full) {
+            constexpr bool P = decltype(pow2)::value, F = decltype(full)::value;
+            if constexpr (F) {
+                // full tile: kTile / 128 pairs per lane (a uniform trip count)
+#pragma unroll 2
+                for (uint32_t t = 0; t < kTile / (2 * kWave); t++) {
+                    const uint32_t j = 2 * lane + t * (2 * kWave);
+                    uint32_t u0, u1, v0, v1;
+                    flush_pair<NARROW, P>(a, stage, ibase, j, u0, u1, v0, v1);
+                    if constexpr (VEC16)
+                        *reinterpret_cast<uint4 *>(out + 2 * j) = make_uint4(u0, v0, u1, v1);
+                    else
+                        store_pair<false>(out, j, kTile, u0, v0, u1, v1);
+                    if constexpr (VLIST) *reinterpret_cast<uint2 *>(a.vlist + off + j) = make_uint2(v0, v1);
+                }
+            } else {
+                for (uint32_t j = 2 * lane; j < tn; j += 2 * kWave) {
+                    uint32_t u0, u1, v0, v1;
+                    flush_pair<NARROW, P>(a, stage, ibase, j, u0, u1, v0, v1);
+                    store_pair<VEC16>(out, j, tn, u0, v0, u1, v1);
+                    if constexpr (VLIST) {
+                        // second endpoints alone, for the degree pipeline (8-byte aligned: j, off even)
+                        if (j + 1 < tn)
+                            *reinterpret_cast<uint2 *>(a.vlist + off + j) = make_uint2(v0, v1);
+                        else
+                            a.vlist[off + j] = v0;
+                    }
+                }
             }
+        };
+        using T = std::true_type;
+        using Fa = std::false_type;
+        if (a.div.pow2) {
+            if (tn == kTile) flush(T{}, T{});
+            else flush(T{}, Fa{});
+        } else {
+            if (tn == kTile) flush(Fa{}, T{});
+            else flush(Fa{}, Fa{});
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();

@@ -78,26 +78,60 @@ __global__ __launch_bounds__(WAVES * 64) void k_gen_batch(BatchArgs a)
 
         uint32_t *out = a.edges + I.out + 2 * off;
         const bool vec16 = (((uintptr_t)(a.edges + I.out)) & 15) == 0;  // off is a multiple of 2 edges
-        for (uint32_t jj = 2 * lane; jj < tn; jj += 2 * kWave) {
-            const uint2 s = *reinterpret_cast<const uint2 *>(stage + jj);
-            uint32_t u0, u1, v0, v1;
-            if (I.narrow) {
-                const uint32_t i0 = (uint32_t)off + jj;
-                u0 = div32(i0, I.div);
-                u1 = div32(i0 + 1, I.div);
-                v0 = div32(s.x, I.div);
-                v1 = div32(s.y, I.div);
+        // The instance's width and divider kind, and whether the tile is full
+        // and 16-byte aligned, are uniform per tile: they select a loop
+        // instead of being tested in it.
+        auto flush = [&](auto narrow_t, auto pow2_t, auto full_t) {
+            constexpr bool NW = decltype(narrow_t)::value, P = decltype(pow2_t)::value,
+                           F = decltype(full_t)::value;
+            auto pair = [&](uint32_t jj, uint32_t &u0, uint32_t &u1, uint32_t &v0, uint32_t &v1) {
+                const uint2 s = *reinterpret_cast<const uint2 *>(stage + jj);
+                if constexpr (NW) {
+                    const uint32_t i0 = (uint32_t)off + jj;
+                    u0 = fdiv32<P>(i0, I.div);
+                    u1 = fdiv32<P>(i0 + 1, I.div);
+                    v0 = fdiv32<P>(s.x, I.div);
+                    v1 = fdiv32<P>(s.y, I.div);
+                } else {
+                    const uint64_t i0 = off + jj;
+                    u0 = (uint32_t)fdiv64<P>(i0, I.div);
+                    u1 = (uint32_t)fdiv64<P>(i0 + 1, I.div);
+                    v0 = s.x;
+                    v1 = s.y;
+                }
+            };
+            if constexpr (F) {
+                // full, aligned tile: TILE / 128 pairs per lane (a uniform trip count)
+#pragma unroll 1
+                for (uint32_t t = 0; t < TILE / (2 * kWave); t++) {
+                    const uint32_t jj = 2 * lane + t * (2 * kWave);
+                    uint32_t u0, u1, v0, v1;
+                    pair(jj, u0, u1, v0, v1);
+                    *reinterpret_cast<uint4 *>(out + 2 * jj) = make_uint4(u0, v0, u1, v1);
+                }
             } else {
-                const uint64_t i0 = off + jj;
-                u0 = (uint32_t)div64(i0, I.div);
-                u1 = (uint32_t)div64(i0 + 1, I.div);
-                v0 = s.x;
-                v1 = s.y;
+                for (uint32_t jj = 2 * lane; jj < tn; jj += 2 * kWave) {
+                    uint32_t u0, u1, v0, v1;
+                    pair(jj, u0, u1, v0, v1);
+                    if (vec16)
+                        store_pair<true>(out, jj, tn, u0, v0, u1, v1);
+                    else
+                        store_pair<false>(out, jj, tn, u0, v0, u1, v1);
+                }
             }
-            if (vec16)
-                store_pair<true>(out, jj, tn, u0, v0, u1, v1);
-            else
-                store_pair<false>(out, jj, tn, u0, v0, u1, v1);
+        };
+        using T = std::true_type;
+        using Fa = std::false_type;
+        const bool full = tn == TILE && vec16;
+        if (I.narrow) {
+            if (I.div.pow2) {
+                if (full) flush(T{}, T{}, T{}); else flush(T{}, T{}, Fa{});
+            } else {
+                if (full) flush(T{}, Fa{}, T{}); else flush(T{}, Fa{}, Fa{});
+            }
+        } else {
+            // 64-bit positions (large instances only): the general loop
+            if (I.div.pow2) flush(Fa{}, T{}, Fa{}); else flush(Fa{}, Fa{}, Fa{});
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
