@@ -345,7 +345,9 @@ int ba_host_divide(uint32_t d, const uint64_t *x, uint64_t *q, uint64_t count);
  * CRC-hash kernels use on 32-bit positions for the paper's hash mod x: two
  * quotient estimates in double precision, each followed by one exact
  * correction.  Writes r[j] = x[j] mod b[j] for count host values, computed
- * that way on the host.  Returns BA_OK, or BA_EINVAL for a NULL array with
+ * that way on the host, from a reciprocal seed with a larger error than the
+ * device's (so the self-test covers the device's error bound).  Returns
+ * BA_OK, or BA_EINVAL for a NULL array with
  * count > 0 or any b[j] = 0.
  */
 int ba_host_mod64(const uint64_t *x, const uint32_t *b, uint32_t *r, uint64_t count);

@@ -668,11 +668,12 @@ template <bool C, bool L, bool N>
 static int launch_model_one(const ModelArgs &a, hipStream_t st)
 {
     uint32_t grid = 0;
-    int rc = persistent_grid(k_gen_model<C, L, N>, kGenBlock, &grid);
+    int rc = persistent_grid(k_gen_model<C, L, N>, kModelBlock<C>, &grid);
     if (rc) return rc;
-    grid = grid_for(a.ntiles, kGenWaves, grid);
-    return launch_timed(BA_KT_GEN, st,
-                        [&] { hipLaunchKernelGGL((k_gen_model<C, L, N>), dim3(grid), dim3(kGenBlock), 0, st, a); });
+    grid = grid_for(a.ntiles, kModelWaves<C>, grid);
+    return launch_timed(BA_KT_GEN, st, [&] {
+        hipLaunchKernelGGL((k_gen_model<C, L, N>), dim3(grid), dim3(kModelBlock<C>), 0, st, a);
+    });
 }
 
 template <bool C, bool L>
@@ -1127,6 +1128,7 @@ int ba_generate_model(uint64_t n, uint32_t d, uint64_t seed, uint64_t n0, uint64
     a.key = make_hash_key(seed);
     a.key64 = seed * kPhi64;
     a.k1 = crc32c_u64(kHostCrcTables.t, 1u, 0);
+    a.khi = crc32c_u64(kHostCrcTables.t, 0u, a.key64 & ~(uint64_t)0xFFFFFFFFu);
     a.div = make_divider(d);
     a.P0 = 2 * m0;
     a.n0 = n0;

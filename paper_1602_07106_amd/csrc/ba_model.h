@@ -17,7 +17,9 @@
 // SSE4.2 crc32 instruction of the paper's hash_crc).  CRC is affine in the
 // register, so crc32c(1, z) = crc32c(0, z) XOR crc32c(1, 0): one table
 // evaluation serves both halves.  The update runs slicing-by-8 from tables
-// held in LDS (8 KiB per block).
+// held in LDS (8 KiB per block).  With positions below 2^32 the high half of
+// z is the key's, whose share of crc32c(0, z) is computed once on the host,
+// so only the four tables of the low bytes are read (4 KiB).
 //
 // Included by ba.hip after the chain loop.
 #pragma once
@@ -56,37 +58,46 @@ __host__ __device__ __forceinline__ uint32_t crc32c_u64(const Tab &t, uint32_t c
            t[3][(v >> 32) & 0xFF] ^ t[2][(v >> 40) & 0xFF] ^ t[1][(v >> 48) & 0xFF] ^ t[0][v >> 56];
 }
 
+// crc32c(0, x) for x whose high word is fixed: the update from register 0
+// is linear over GF(2) in x, so it is the update of the low word alone
+// (the tables of its four bytes, t[7]..t[4], passed as lo4[3]..lo4[0])
+// XOR hi_part, the update of the high word alone (high << 32).
+template <class Tab>
+__host__ __device__ __forceinline__ uint32_t crc32c0_low_word(const Tab &lo4, uint32_t lo, uint32_t hi_part)
+{
+    return lo4[3][lo & 0xFF] ^ lo4[2][(lo >> 8) & 0xFF] ^ lo4[1][(lo >> 16) & 0xFF] ^ lo4[0][lo >> 24] ^ hi_part;
+}
+
 // x mod b for 1 <= b < 2^32, exact; there is no 64-by-32-bit division
 // instruction.  Two steps, each with a quotient estimate in double precision:
 // r1 = hi mod b, then (r1 * 2^32 + lo) mod b, whose quotient is below 2^32.
-// With y within 2^-48 of 1/b (a 2^-23 seed refined twice by Newton's
-// iteration), the estimate num * y is within 2^-17 of num / b: num converts
-// exactly below 2^53, and above it b > num / 2^32 > 2^21 bounds the
-// conversion's share of the error by 2^-21.  The truncated (and clamped)
-// estimate is therefore q - 1, q or q + 1, and one signed correction of
-// num - q_est * b gives the remainder.
+// The reciprocal seed (float(b) rounded, then a 1-ulp reciprocal) is within
+// 1.5 * 2^-23 of 1/b; one Newton step squares that to below 2^-44, so num * y
+// is within 2^-12 of num / b < 2^32.  The second step forms num * y as
+// r1 * (2^32 y) + lo * y (one rounded product, one rounded fma: 2^-20 more).
+// The truncated (and clamped) estimate is therefore q - 1, q or q + 1, so
+// num - q_est * b lies in [-b, 2b) and one signed correction, taken by
+// selects, gives the remainder.  The host build perturbs its (correctly
+// rounded) seed by 2^-22, a larger error than the device's, so a host
+// self-test covers the device's error bound.
 __host__ __device__ __forceinline__ uint32_t mod_u64_u32(uint64_t x, uint32_t b)
 {
     const double bd = (double)b;
 #if defined(__HIP_DEVICE_COMPILE__)
     double y = (double)__builtin_amdgcn_rcpf((float)b);
 #else
-    double y = (double)(1.0f / (float)b);
+    double y = (double)(1.0f / (float)b) * ((b & 1u) ? 1.0 + 0x1p-22 : 1.0 - 0x1p-22);
 #endif
     y = fma(fma(-bd, y, 1.0), y, y);
-    y = fma(fma(-bd, y, 1.0), y, y);
-    auto reduce = [&](uint64_t num) -> uint32_t {  // num < b * 2^32
-        const double qd = (double)num * y;
-        const uint32_t q = qd >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)qd;
-        int64_t r = (int64_t)(num - (uint64_t)q * b);
-        if (r < 0)
-            r += b;
-        else if (r >= (int64_t)b)
-            r -= b;
-        return (uint32_t)r;
+    auto fix = [&](uint64_t num, double qd) -> uint32_t {  // num < b * 2^32, qd >= 0
+        const uint32_t q = (uint32_t)fmin(qd, 4294967295.0);
+        const int64_t r = (int64_t)(num - (uint64_t)q * b);  // in [-b, 2b)
+        const uint32_t rl = (uint32_t)r;
+        return r < 0 ? rl + b : (r >= (int64_t)b ? rl - b : rl);
     };
-    const uint32_t r1 = reduce(x >> 32);
-    return reduce(((uint64_t)r1 << 32) | (uint32_t)x);
+    const uint32_t hi = (uint32_t)(x >> 32), lo = (uint32_t)x;
+    const uint32_t r1 = fix(hi, (double)hi * y);
+    return fix(((uint64_t)r1 << 32) | lo, fma((double)r1, y * 4294967296.0, (double)lo * y));
 }
 
 enum : uint32_t { kModelNoLoops = 1, kModelCrc = 2 };
@@ -94,6 +105,8 @@ enum : uint32_t { kModelNoLoops = 1, kModelCrc = 2 };
 struct ModelArgs {
     HashKey key;
     uint32_t k1;       // crc32c(1, 0): the register-1 offset of the crc hash
+    uint32_t khi;      // crc32c(0, (key64 >> 32) << 32): with positions below 2^32 the
+                       // hashed word's high half is key64's, a constant share
     Divider div;
     uint64_t key64;    // seed * phi64 (the crc hash XORs it into r)
     uint64_t P0;       // 2*m0: first position of the new edges
@@ -105,70 +118,143 @@ struct ModelArgs {
 
 // NARROW: every position of the launch (2*m0 + 2*(n-n0)*d) is below 2^32,
 // so positions, bounds and the fmix high product stay 32-bit.
+// Block size: the CRC variants hold their tables in LDS per block (4 KiB
+// on 32-bit positions, 8 KiB on 64-bit), so they run 8 waves a block to
+// share them: 40 KiB blocks still fill a CU's 160 KiB at 8 waves per SIMD,
+// where 4-wave blocks of 24 KiB stop at 6.  The others run the generator's
+// 4 waves.
+template <bool CRC>
+constexpr int kModelBlock = CRC ? 512 : kGenBlock;
+template <bool CRC>
+constexpr int kModelWaves = kModelBlock<CRC> / kWave;
+
 template <bool CRC, bool NOLOOPS, bool NARROW>
-__global__ __launch_bounds__(kGenBlock) void k_gen_model(ModelArgs a)
+__global__ __launch_bounds__(kModelBlock<CRC>) void k_gen_model(ModelArgs a)
 {
+    constexpr int kBlock = kModelBlock<CRC>, kWaves = kModelWaves<CRC>;
     using R = typename std::conditional<NARROW, uint32_t, uint64_t>::type;
-    __shared__ uint32_t stage_all[kGenWaves][kTile];
-    __shared__ uint32_t crc_t[CRC ? 8 : 1][256];
+    __shared__ uint32_t stage_all[kWaves][kTile];
+    // CRC tables in LDS: all eight for 64-bit positions; with 32-bit
+    // positions only the four of the low word's bytes (t[4..7])
+    constexpr int kCrcRows = CRC ? (NARROW ? 4 : 8) : 1;
+    __shared__ uint32_t crc_t[kCrcRows][256];
     if constexpr (CRC) {
-        for (uint32_t j = threadIdx.x; j < 8 * 256; j += kGenBlock) crc_t[j / 256][j % 256] = kCrcTables.t[j / 256][j % 256];
+        for (uint32_t j = threadIdx.x; j < kCrcRows * 256; j += kBlock)
+            crc_t[j / 256][j % 256] = kCrcTables.t[8 - kCrcRows + j / 256][j % 256];
         __syncthreads();
     }
     const uint32_t lane = __lane_id();
-    const uint32_t wv = threadIdx.x / kWave;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform: scalar loops
     uint32_t *stage = stage_all[wv];
-    const uint64_t wstride = (uint64_t)gridDim.x * kGenWaves;
+    const uint64_t wstride = (uint64_t)gridDim.x * kWaves;
     const R P0 = (R)a.P0;
+    const uint32_t stop_min = 0x80000000u - (uint32_t)(a.P0 >> 1);  // 32-bit positions only
+    // 16-byte stores when the output is 16-byte aligned (tiles start at even edges)
+    const bool vec16 = (((uintptr_t)a.edges) & 15) == 0;
 
-    // floor(x / d) in the width of the launch
-    auto divd = [&](R x) -> R {
-        if constexpr (NARROW) return div32(x, a.div);
-        else return div64(x, a.div);
-    };
-    // draw bound of the edge whose second endpoint sits at odd r >= P0
-    auto bound = [&](R r) -> R {
-        if constexpr (NOLOOPS) return P0 + 2 * (R)a.div.d * divd((r - P0) >> 1);  // (r-P0-1)/2 = edge index
-        else return r;
-    };
-    auto hash = [&](R r) -> R {
-        const R b = bound(r);
-        if constexpr (CRC) {
-            const uint32_t c0 = crc32c_u64(crc_t, 0u, (uint64_t)r ^ a.key64);
-            const uint64_t h = ((uint64_t)c0 << 32) + (uint64_t)(c0 ^ a.k1);
-            if constexpr (NARROW) return mod_u64_u32(h, b);
-            else return h % b;
-        } else if constexpr (NARROW) {
-            return hash_narrow_bounded(r, b, a.key);
-        } else {
-            return hash_bounded(r, b, a.key);
-        }
-    };
-    auto stop = [&](R r) { return r < P0 || !((uint32_t)r & 1u); };
-    auto node = [&](R r) -> uint32_t { return r < P0 ? a.S[r] : (uint32_t)(a.n0 + divd((r - P0) >> 1)); };
+    // One tile with the divider's kind fixed at compile time: the kind is
+    // uniform, so it selects a copy of the whole tile loop body instead of
+    // being tested at every division.
+    auto run_tile = [&](auto pow2, uint64_t tile) {
+        constexpr bool P = decltype(pow2)::value;
+        // floor(x / d) in the width of the launch
+        auto divd = [&](R x) -> R {
+            if constexpr (NARROW) return fdiv32<P>(x, a.div);
+            else return fdiv64<P>(x, a.div);
+        };
+        // draw bound of the edge whose second endpoint sits at odd r >= P0
+        auto bound = [&](R r) -> R {
+            if constexpr (NOLOOPS) return P0 + 2 * (R)a.div.d * divd((r - P0) >> 1);  // (r-P0-1)/2 = edge index
+            else return r;
+        };
+        auto hash = [&](R r) -> R {
+            const R b = bound(r);
+            if constexpr (CRC) {
+                uint32_t c0;
+                if constexpr (NARROW)
+                    c0 = crc32c0_low_word(crc_t, (uint32_t)r ^ (uint32_t)a.key64, a.khi);
+                else
+                    c0 = crc32c_u64(crc_t, 0u, (uint64_t)r ^ a.key64);
+                const uint64_t h = ((uint64_t)c0 << 32) + (uint64_t)(c0 ^ a.k1);
+                if constexpr (NARROW) return mod_u64_u32(h, b);
+                else return h % b;
+            } else if constexpr (NARROW) {
+                return hash_narrow_bounded(r, b, a.key);
+            } else {
+                return hash_bounded(r, b, a.key);
+            }
+        };
+        // final position: even, or a seed position (r < P0).  On 32-bit
+        // positions, with P0 even, that is one unsigned compare: w = (r XOR 1)
+        // - P0 has w's low bit set iff r is even, and rotating it right by one
+        // maps the even r to [2^31, 2^32), the odd r >= P0 to [0, 2^31 - P0/2)
+        // and the odd r < P0 (w wrapped) to [2^31 - P0/2, 2^31).
+        auto stop = [&](R r) {
+            if constexpr (NARROW) {
+                const uint32_t w = (r ^ 1u) - P0;
+                return ((w >> 1) | (w << 31)) >= stop_min;
+            } else {
+                return r < P0 || !((uint32_t)r & 1u);
+            }
+        };
+        auto node = [&](R r) -> uint32_t {
+            return r < P0 ? a.S[r] : (uint32_t)(a.n0 + divd((r - P0) >> 1));
+        };
 
-    for (uint64_t tile = (uint64_t)blockIdx.x * kGenWaves + wv; tile < a.ntiles; tile += wstride) {
         const uint64_t off = tile * kTile;
         const uint32_t tn = (uint32_t)min((uint64_t)kTile, a.count - off);
         const uint64_t ibase = a.begin + off;
-        chain_tile_until(stage, tn, lane, (R)(a.P0 + 2 * ibase + 1), hash, stop, node);
+        // 32-bit positions: the stage holds the final position r and the
+        // flush maps it to its node, with every lane busy; 64-bit: the node.
+        if constexpr (NARROW)
+            chain_tile_until(stage, tn, lane, (R)(a.P0 + 2 * ibase + 1), hash, stop, [](R r) { return r; });
+        else
+            chain_tile_until(stage, tn, lane, (R)(a.P0 + 2 * ibase + 1), hash, stop, node);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         uint32_t *out = a.edges + 2 * off;
-        const bool vec16 = (((uintptr_t)out) & 15) == 0;
-        for (uint32_t j = 2 * lane; j < tn; j += 2 * kWave) {
+        auto pair_at = [&](uint32_t j, uint32_t &u0, uint32_t &v0, uint32_t &u1, uint32_t &v1) {
             const uint2 s = *reinterpret_cast<const uint2 *>(stage + j);
-            const uint32_t u0 = (uint32_t)(a.n0 + divd((R)(ibase + j)));
-            const uint32_t u1 = (uint32_t)(a.n0 + divd((R)(ibase + j + 1)));
-            if (vec16)
-                store_pair<true>(out, j, tn, u0, s.x, u1, s.y);
-            else
-                store_pair<false>(out, j, tn, u0, s.x, u1, s.y);
+            u0 = (uint32_t)(a.n0 + divd((R)(ibase + j)));
+            u1 = (uint32_t)(a.n0 + divd((R)(ibase + j + 1)));
+            if constexpr (NARROW) {
+                v0 = node(s.x);
+                v1 = node(s.y);
+            } else {
+                v0 = s.x;
+                v1 = s.y;
+            }
+        };
+        if (tn == kTile && vec16) {
+            // full tile: kTile / 128 pairs per lane, no partial-pair checks
+#pragma unroll 2
+            for (uint32_t t = 0; t < kTile / (2 * kWave); t++) {
+                const uint32_t j = 2 * lane + t * (2 * kWave);
+                uint32_t u0, v0, u1, v1;
+                pair_at(j, u0, v0, u1, v1);
+                *reinterpret_cast<uint4 *>(out + 2 * j) = make_uint4(u0, v0, u1, v1);
+            }
+        } else {
+            for (uint32_t j = 2 * lane; j < tn; j += 2 * kWave) {
+                uint32_t u0, v0, u1, v1;
+                pair_at(j, u0, v0, u1, v1);
+                if (vec16)
+                    store_pair<true>(out, j, tn, u0, v0, u1, v1);
+                else
+                    store_pair<false>(out, j, tn, u0, v0, u1, v1);
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+
+    for (uint64_t tile = (uint64_t)blockIdx.x * kWaves + wv; tile < a.ntiles; tile += wstride) {
+        if (a.div.pow2)
+            run_tile(std::true_type{}, tile);
+        else
+            run_tile(std::false_type{}, tile);
     }
 }
 

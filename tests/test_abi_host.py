@@ -84,11 +84,14 @@ def _host_mod(xs, bs):
 
 def test_exact_remainder_on_boundaries():
     """x mod b for the CRC hash (64-bit x, 32-bit b): divisors from 1 to
-    2^32 - 1 around the error-bound switch points (2^12, 2^21), dividends at
-    multiples of b, around 2^53 and up to 2^64 - 1."""
+    2^32 - 1, among them those whose float rounding is coarsest (2^24 + 1,
+    2^32 - 2^7 - 1: the reciprocal seed's largest error), dividends at
+    multiples of b, around 2^53 and up to 2^64 - 1.  The host runs the
+    device's algorithm with a seed error larger than the device's."""
     M = (1 << 64) - 1
-    divs = [1, 2, 3, 7, 4095, 4096, 4097, (1 << 21) - 1, 1 << 21, (1 << 21) + 1, 1000003, (1 << 31) - 1, 1 << 31,
-            (1 << 31) + 1, (1 << 32) - 3, (1 << 32) - 1]
+    divs = [1, 2, 3, 7, 4095, 4096, 4097, (1 << 21) - 1, 1 << 21, (1 << 21) + 1, 1000003, (1 << 24) - 1,
+            (1 << 24) + 1, (1 << 24) + 3, (3 << 23) + 1, (1 << 31) - 1, 1 << 31, (1 << 31) + 1,
+            (1 << 32) - (1 << 7) - 1, (1 << 32) - 3, (1 << 32) - 1]
     xs, bs = [], []
     for b in divs:
         vals = {0, 1, b - 1, b, b + 1, (1 << 32) - 1, 1 << 32, (1 << 53) - 1, 1 << 53, (1 << 53) + 1, M - 1, M}
