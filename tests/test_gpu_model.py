@@ -109,3 +109,26 @@ def test_model_at_the_32_bit_position_boundary(m0):
         torch.cuda.synchronize()
         ref, _ = oracle.model_edges_range(n0, m0, S, d, seed, 0, b, 2000)
         assert np.array_equal(out.cpu().numpy().view(np.uint32), ref)
+
+
+@pytest.mark.parametrize("no_loops,h", FLAGS)
+def test_model_with_a_large_seed_graph_near_2_32(no_loops, h):
+    # 2*m0 = 3*2^23 seed positions and new positions up to just below 2^32:
+    # the one-compare stop test at a large P0, chains that end in the seed
+    # graph often (first range) and rarely (last range), and seed IDs of
+    # every size (IDs >= n0 pass through unchanged)
+    n0, m0, d, seed = 1000, 3 << 22, 5, 13
+    n = n0 + ((1 << 32) - 2 * m0) // (2 * d)
+    rng = np.random.default_rng(17)
+    S = rng.integers(0, n0, 2 * m0).astype(np.uint32)
+    big = rng.integers(0, 2 * m0, 4096)
+    S[big] = rng.integers(0, 1 << 32, big.size, dtype=np.uint64).astype(np.uint32)
+    St = torch.from_numpy(S.view(np.int32)).to("cuda")
+    m = (n - n0) * d
+    assert 2 * m0 + 2 * m <= 1 << 32
+    for b, c in [(0, 6000), (m // 2 + 3, 3001), (m - 4097, 4097)]:
+        _say("model large seed", no_loops, h, b, c)
+        out = ba.generate_model(n, d, seed, n0=n0, seed_edges=St, no_self_loops=no_loops, hash=h, begin=b, count=c)
+        torch.cuda.synchronize()
+        ref, _ = oracle.model_edges_range(n0, m0, S, d, seed, _oflags(no_loops, h), b, c)
+        assert np.array_equal(out.cpu().numpy().view(np.uint32), ref)
