@@ -256,14 +256,17 @@ int ba_batch_plan_rounds(uint32_t count, const uint64_t *n, const uint32_t *d, u
  * least 4 KiB; results and batch tables live there) and a stream, and
  * records the server's time origin on that stream.  ba_server_submit
  * queues a request on the host (BA_ERANGE / BA_EINVAL for graphs the
- * matching call refuses) and returns its ticket.  ba_server_pump retires
+ * matching call refuses; BA_ERANGE when the result's byte count would not
+ * fit 64 bits) and returns its ticket.  ba_server_pump retires
  * finished steps and, when fewer than max_inflight steps are in flight,
  * launches one more: it admits queued requests in arrival order while their
  * outputs fit the free arena (admission by HBM bytes), runs every admitted
  * edge request as one batched persistent launch and every degree request
  * as a streaming launch, and records one event for the step (*launched =
  * requests admitted).  It never blocks on the GPU.  A request that cannot
- * fit even an empty arena is marked BA_JOB_FAILED.
+ * fit even an empty arena is marked BA_JOB_FAILED.  If a launch of the step
+ * fails, pump waits for the stream, marks the step's requests
+ * BA_JOB_FAILED, frees their arena space and returns the error.
  * ba_server_poll reports a ticket's state and, once BA_JOB_READY, the GPU
  * completion time of its step in ms after the time origin and the byte
  * offset/size of its result in the arena.  ba_server_completed hands out

@@ -127,13 +127,18 @@ def _check(fn: str, status: int) -> None:
         raise BAError(fn, status)
 
 
-def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+def _ptr(t: Optional[torch.Tensor], dev: Optional[torch.device] = None) -> Optional[int]:
+    """t's device address; t must be a contiguous device tensor (on dev, when given)."""
     if t is None:
         return None
     if not t.is_cuda:
         raise ValueError("expected a device tensor")
     if not t.is_contiguous():
         raise ValueError("expected a contiguous tensor")
+    if dev is not None:
+        want = dev.index if dev.index is not None else torch.cuda.current_device()
+        if t.device.index != want:
+            raise ValueError(f"expected a tensor on cuda:{want}, got one on {t.device}")
     return t.data_ptr()
 
 
@@ -194,12 +199,12 @@ def generate(
             raise ValueError("deg_out must be int32 with n elements")
     with torch.cuda.device(dev):
         if deg is None:
-            _check("ba_generate", lib().ba_generate(n, d, seed, _ptr(out), None, _stream(dev)))
+            _check("ba_generate", lib().ba_generate(n, d, seed, _ptr(out, dev), None, _stream(dev)))
         else:
             w, wb = _ws_arg(ws, n, d, m, dev)
             _check(
                 "ba_generate_ws",
-                lib().ba_generate_ws(n, d, seed, _ptr(out), _ptr(deg), _ptr(w), wb, _stream(dev)),
+                lib().ba_generate_ws(n, d, seed, _ptr(out, dev), _ptr(deg, dev), _ptr(w, dev), wb, _stream(dev)),
             )
     return out, deg
 
@@ -229,13 +234,13 @@ def generate_range(
         if deg is None:
             _check(
                 "ba_generate_range",
-                lib().ba_generate_range(n, d, seed, begin, count, _ptr(out), None, _stream(dev)),
+                lib().ba_generate_range(n, d, seed, begin, count, _ptr(out, dev), None, _stream(dev)),
             )
         else:
             w, wb = _ws_arg(ws, n, d, count, dev)
             _check(
                 "ba_generate_range_ws",
-                lib().ba_generate_range_ws(n, d, seed, begin, count, _ptr(out), _ptr(deg), _ptr(w), wb,
+                lib().ba_generate_range_ws(n, d, seed, begin, count, _ptr(out, dev), _ptr(deg, dev), _ptr(w, dev), wb,
                                            _stream(dev)),
             )
     return out
@@ -263,7 +268,7 @@ def generate_range_u64(n: int, d: int, seed: int, begin: int, count: int, *, dev
     with torch.cuda.device(dev):
         _check(
             "ba_generate_range_u64",
-            lib().ba_generate_range_u64(n, d, seed, begin, count, _ptr(out), _stream(dev)),
+            lib().ba_generate_range_u64(n, d, seed, begin, count, _ptr(out, dev), _stream(dev)),
         )
     return out
 
@@ -275,7 +280,7 @@ def degrees(n: int, d: int, seed: int, first_k: int, *, device=None) -> Tuple[to
     deg = torch.empty(first_k, dtype=torch.int64, device=dev)
     cs = torch.empty(1, dtype=torch.int64, device=dev)
     with torch.cuda.device(dev):
-        _check("ba_degrees", lib().ba_degrees(n, d, seed, first_k, _ptr(deg), _ptr(cs), _stream(dev)))
+        _check("ba_degrees", lib().ba_degrees(n, d, seed, first_k, _ptr(deg, dev), _ptr(cs, dev), _stream(dev)))
     return deg, int(cs.item()) & ((1 << 64) - 1)
 
 
@@ -300,7 +305,7 @@ def degrees_range(
     with torch.cuda.device(dev):
         _check(
             "ba_degrees_range",
-            lib().ba_degrees_range(n, d, seed, begin, count, first_k, _ptr(deg), _ptr(cs), _stream(dev)),
+            lib().ba_degrees_range(n, d, seed, begin, count, first_k, _ptr(deg, dev), _ptr(cs, dev), _stream(dev)),
         )
 
 
@@ -550,7 +555,6 @@ def generate_model(n: int, d: int, seed: int, *, n0: int = 0, seed_edges: Option
         if seed_edges.dtype != torch.int32 or seed_edges.numel() % 2:
             raise ValueError("seed_edges must be int32 with 2*m0 elements")
         m0 = seed_edges.numel() // 2
-        sp = _ptr(seed_edges)
         device = seed_edges.device if device is None else device
     if count is None:
         count = (n - n0) * d - begin
@@ -559,8 +563,9 @@ def generate_model(n: int, d: int, seed: int, *, n0: int = 0, seed_edges: Option
         out = torch.empty((count, 2), dtype=torch.int32, device=dev)
     elif out.dtype != torch.int32 or out.numel() != 2 * count:
         raise ValueError("out must be int32 with 2*count elements")
+    sp = _ptr(seed_edges, dev)
     flags = (NO_SELF_LOOPS if no_self_loops else 0) | (HASH_CRC if hash == "crc" else 0)
     with torch.cuda.device(dev):
         _check("ba_generate_model", lib().ba_generate_model(n, d, seed, n0, m0, sp, flags, begin, count,
-                                                            _ptr(out) if count else None, _stream(dev)))
+                                                            _ptr(out, dev) if count else None, _stream(dev)))
     return out

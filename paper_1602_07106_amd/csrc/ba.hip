@@ -979,7 +979,7 @@ int ba_batch_plan_rounds(uint32_t count, const uint64_t *n, const uint32_t *d, u
     uint64_t off = 0;
     for (uint32_t j = 0; j < count; j++) {
         uint64_t m;
-        if (!graph_fits(n[j], d[j], &m) || n[j] > ((uint64_t)1 << 32)) return BA_ERANGE;
+        if (!graph_fits(n[j], d[j], &m) || n[j] > ((uint64_t)1 << 32) || m > (UINT64_MAX - 3) / 2) return BA_ERANGE;
         const uint64_t need = (2 * m + 3) & ~(uint64_t)3;  // each instance starts 16-byte aligned
         if (need > round_elems) return BA_EINVAL;
         if (off + need > round_elems) {
@@ -1035,10 +1035,12 @@ int ba_server_submit(ba_server *s, const ba_request *r, uint64_t *ticket)
     if (!s || !r || !ticket) return BA_EINVAL;
     uint64_t m;
     if (!graph_fits(r->n, r->d, &m)) return BA_ERANGE;
+    // result sizes (8*m, 8*(first_k+1) bytes) must fit 64 bits
     if (r->kind == BA_REQ_EDGES) {
-        if (r->n > ((uint64_t)1 << 32)) return BA_ERANGE;
+        if (r->n > ((uint64_t)1 << 32) || m > UINT64_MAX / 8) return BA_ERANGE;
     } else if (r->kind == BA_REQ_DEGREES) {
         if (r->first_k > r->n) return BA_EINVAL;
+        if (r->first_k >= UINT64_MAX / 8) return BA_ERANGE;
     } else {
         return BA_EINVAL;
     }

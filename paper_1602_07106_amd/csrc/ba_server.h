@@ -25,9 +25,13 @@ namespace ba {
 // First-fit allocator over [0, bytes) of the arena, 256-byte granules.
 class ArenaAlloc {
   public:
-    explicit ArenaAlloc(uint64_t bytes) { if (bytes >= 256) free_[0] = bytes & ~(uint64_t)255; }
+    explicit ArenaAlloc(uint64_t bytes) : total_(bytes & ~(uint64_t)255)
+    {
+        if (total_) free_[0] = total_;
+    }
     bool alloc(uint64_t bytes, uint64_t *off)
     {
+        if (bytes > total_) return false;  // also keeps the rounding below from wrapping
         bytes = align256(bytes ? bytes : 1);
         for (auto it = free_.begin(); it != free_.end(); ++it) {
             if (it->second >= bytes) {
@@ -62,6 +66,7 @@ class ArenaAlloc {
     uint64_t used() const { return used_; }
 
   private:
+    uint64_t total_;
     std::map<uint64_t, uint64_t> free_;
     uint64_t used_ = 0;
 };
@@ -181,6 +186,24 @@ static int server_launch_step(ba_server *s, uint32_t *launched)
     }
     ServerStep st;
     int rc = BA_OK;
+    // A launch of the step failed: part of it may already be queued, so wait
+    // for the stream, then fail the step's requests and free what they held.
+    auto fail_step = [&](int err) {
+        (void)hipStreamSynchronize(s->stream);
+        for (const auto *list : {&edge_jobs, &deg_jobs}) {
+            for (uint64_t j : *list) {
+                ServerJob &J = *server_job(s, j);
+                s->alloc.release(J.out_off, J.out_bytes);
+                J.state = BA_JOB_FAILED;
+                s->completed.push_back(j);
+            }
+        }
+        if (st.table_bytes) s->alloc.release(st.table_off, st.table_bytes);
+        if (st.slot >= 0) s->free_slots.push_back(st.slot);
+        if (st.ev) (void)hipEventDestroy(st.ev);
+        *launched = 0;
+        return err;
+    };
     const uint32_t ne = (uint32_t)edge_jobs.size();
     if (ne) {
         const BatchLayout L = batch_layout(ne);
@@ -221,23 +244,23 @@ static int server_launch_step(ba_server *s, uint32_t *launched)
         for (int t = 0; t < 3; t++) T[t][ne] = tiles[t];
         if ((rc = hip_check(hipMemcpyAsync(s->arena + st.table_off, stage, L.bytes, hipMemcpyHostToDevice,
                                            s->stream))))
-            return rc;
+            return fail_step(rc);
         ba_batch_info info{};
         info.count = ne;
         for (int t = 0; t < 3; t++) info.tiles[t] = tiles[t];
         info.edges_len = s->arena_bytes / 4;
         if ((rc = ba_batch_launch(&info, s->arena + st.table_off, (uint32_t *)s->arena, s->arena_bytes / 4,
                                   s->stream)))
-            return rc;
+            return fail_step(rc);
     }
     for (uint64_t j : deg_jobs) {
         const ServerJob &J = *server_job(s, j);
         uint64_t *deg = (uint64_t *)(s->arena + J.out_off);
         if ((rc = ba_degrees(J.req.n, J.req.d, J.req.seed, J.req.first_k, deg, deg + J.req.first_k, s->stream)))
-            return rc;
+            return fail_step(rc);
     }
-    if ((rc = hip_check(hipEventCreate(&st.ev)))) return rc;
-    if ((rc = hip_check(hipEventRecord(st.ev, s->stream)))) return rc;
+    if ((rc = hip_check(hipEventCreate(&st.ev)))) return fail_step(rc);
+    if ((rc = hip_check(hipEventRecord(st.ev, s->stream)))) return fail_step(rc);
     for (uint64_t j : edge_jobs) st.jobs.push_back(j);
     for (uint64_t j : deg_jobs) st.jobs.push_back(j);
     for (uint64_t j : st.jobs) server_job(s, j)->state = BA_JOB_RUNNING;

@@ -92,6 +92,16 @@ def test_server_validation():
         srv.submit_edges((1 << 32) + 1, 1, 0)  # uint32 IDs need n <= 2^32
     with pytest.raises(ba.BAError):
         srv.submit_degrees(10, 2, 0, 11)  # first_k > n
+    # result sizes that do not fit 64 bits are refused, not wrapped
+    with pytest.raises(ba.BAError):
+        srv.submit_edges(1 << 32, 1 << 30, 0)  # 8 * 2^62 bytes
+    with pytest.raises(ba.BAError):
+        srv.submit_degrees(1 << 62, 1, 0, 1 << 61)  # 8 * (2^61 + 1) bytes
+    # representable but larger than the arena: fails at admission, launches nothing
+    big = srv.submit_degrees(1 << 40, 1, 0, 1 << 40)
+    while srv.poll(big)[0] != ba.JOB_FAILED:
+        srv.pump()
+    srv.release(big)
     t = srv.submit_edges(100, 2, 5)
     with pytest.raises(ba.BAError):
         srv.release(t)  # not ready yet
