@@ -39,13 +39,14 @@ VALU_PEAK = 256 * 64 * 2.4e9               # 32-bit lane-cycles/s: 256 CUs x 64 
 #  narrow (r < 2^32) evaluation, plus fixed cycles per edge; it writes the
 #  8-byte edge pair and the 4-byte target of the degree pipeline;
 #  partition: reads the 4-byte target, writes a 2-byte local index;
-#  histogram: reads the 2-byte index; adds into the 4-byte count of each node.
+#  histogram: reads the 2-byte index; writes the 4-byte count of each node
+#  (a whole graph's counts start from d, so they are stored, not read back).
 HASH_PER_EDGE = 2147478402 / M
 CYCLES_PER_HASH = 17.0
 CYCLES_PER_EDGE = 2.0
 GEN_BYTES_PER_EDGE = 12.0
 PART_BYTES_PER_EDGE = 6.0
-HIST_BYTES = 2.0 * M + 8.0 * N
+HIST_BYTES = 2.0 * M + 4.0 * N
 KERNEL_NAMES = {
     "gen": "k_gen_u32 (chain + edge pairs + target list)",
     "part": "k_deg_part (radix partition of targets)",

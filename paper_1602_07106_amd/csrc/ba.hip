@@ -491,7 +491,7 @@ static uint64_t deg_piece(uint64_t n, uint64_t count, uint64_t ws_bytes)
 // scan, histograms.  First endpoints are the caller's (a fill of d or the
 // closed-form range counts).
 static int degrees_of_targets(uint64_t n, uint32_t d, uint64_t begin, uint64_t count, uint32_t *deg, void *ws,
-                              hipStream_t st)
+                              bool fresh, hipStream_t st)
 {
     uint32_t P = 0;
     int rc = persistent_grid(k_deg_part, kPBlock, &P);
@@ -504,6 +504,7 @@ static int degrees_of_targets(uint64_t n, uint32_t d, uint64_t begin, uint64_t c
     a.deg = deg;
     a.ws = (unsigned char *)ws;
     a.scale = deg_cap_scale();
+    a.fresh = fresh ? 1u : 0u;
     if ((rc = launch_timed(BA_KT_OTHER, st, [&] { hipLaunchKernelGGL(k_deg_plan, dim3(1), dim3(1024), 0, st, a); })))
         return rc;
     for (uint32_t w = 0; w < a.p.NW; w++) {
@@ -512,25 +513,30 @@ static int degrees_of_targets(uint64_t n, uint32_t d, uint64_t begin, uint64_t c
                                [&] { hipLaunchKernelGGL(k_deg_part, dim3(P), dim3(kPBlock), 0, st, a); })))
             return rc;
     }
-    if (count % kPChunk) {
-        const uint32_t tb = (uint32_t)((count % kPChunk + 255) / 256);
-        if ((rc = launch_timed(BA_KT_OTHER, st, [&] { hipLaunchKernelGGL(k_deg_tail, dim3(tb), dim3(256), 0, st, a); })))
-            return rc;
-    }
     if ((rc = launch_timed(BA_KT_OTHER, st,
                            [&] { hipLaunchKernelGGL(k_deg_tot, dim3(a.p.NBsub), dim3(256), 0, st, a); })))
         return rc;
     if ((rc = launch_timed(BA_KT_OTHER, st, [&] { hipLaunchKernelGGL(k_deg_scan, dim3(1), dim3(1024), 0, st, a); })))
         return rc;
     const uint32_t parts_max = (uint32_t)((uint64_t)a.p.NBsub + (count + kHPart - 1) / kHPart + 1);
-    return launch_timed(BA_KT_HIST, st,
-                        [&] { hipLaunchKernelGGL(k_deg_hist, dim3(parts_max), dim3(kHBlock), 0, st, a); });
+    if ((rc = launch_timed(BA_KT_HIST, st,
+                           [&] { hipLaunchKernelGGL(k_deg_hist, dim3(parts_max), dim3(kHBlock), 0, st, a); })))
+        return rc;
+    // the tail's atomics after the histogram, which may store single-part counts directly
+    if (count % kPChunk) {
+        const uint32_t tb = (uint32_t)((count % kPChunk + 255) / 256);
+        if ((rc = launch_timed(BA_KT_OTHER, st, [&] { hipLaunchKernelGGL(k_deg_tail, dim3(tb), dim3(256), 0, st, a); })))
+            return rc;
+    }
+    return BA_OK;
 }
 
 // Edges [begin, begin+count) written to `edges`, their second endpoints
-// added to deg, pass by pass.
+// added to deg, pass by pass.  fresh: deg[v] = d for every node (a whole
+// graph's first endpoints, just filled), so the first pass may store counts
+// without reading deg.
 static int gen_with_degrees(uint64_t n, uint32_t d, uint64_t seed, uint64_t begin, uint64_t count,
-                            uint32_t *edges, uint32_t *deg, void *ws, uint64_t ws_bytes, hipStream_t st)
+                            uint32_t *edges, uint32_t *deg, void *ws, uint64_t ws_bytes, bool fresh, hipStream_t st)
 {
     if (count == 0) return BA_OK;
     const uint64_t piece = deg_piece(n, count, ws_bytes);
@@ -541,7 +547,7 @@ static int gen_with_degrees(uint64_t n, uint32_t d, uint64_t seed, uint64_t begi
         int rc = launch_gen_u32(begin + done, C, d, seed, edges + 2 * done, st,
                                 (uint32_t *)((unsigned char *)ws + p.o_V));
         if (rc) return rc;
-        rc = degrees_of_targets(n, d, begin + done, C, deg, ws, st);
+        rc = degrees_of_targets(n, d, begin + done, C, deg, ws, fresh && done == 0, st);
         if (rc) return rc;
     }
     return BA_OK;
@@ -549,7 +555,7 @@ static int gen_with_degrees(uint64_t n, uint32_t d, uint64_t seed, uint64_t begi
 
 // Workspace from the stream-ordered allocator for calls that bring none.
 static int gen_with_degrees_alloc(uint64_t n, uint32_t d, uint64_t seed, uint64_t begin, uint64_t count,
-                                  uint32_t *edges, uint32_t *deg, hipStream_t st)
+                                  uint32_t *edges, uint32_t *deg, bool fresh, hipStream_t st)
 {
     if (count == 0) return BA_OK;
     const uint64_t piece = count < kPieceMax ? count : kPieceMax;
@@ -557,7 +563,7 @@ static int gen_with_degrees_alloc(uint64_t n, uint32_t d, uint64_t seed, uint64_
     void *ws = nullptr;
     int rc = hip_check(hipMallocAsync(&ws, bytes, st));
     if (rc) return rc;
-    rc = gen_with_degrees(n, d, seed, begin, count, edges, deg, ws, bytes, st);
+    rc = gen_with_degrees(n, d, seed, begin, count, edges, deg, ws, bytes, fresh, st);
     const int rc2 = hip_check(hipFreeAsync(ws, st));
     return rc ? rc : rc2;
 }
@@ -717,7 +723,7 @@ int ba_generate(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint32_t
     if (m && !edges) return BA_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     if ((rc = fill_first_endpoints_whole(n, d, deg, st))) return rc;
-    if (deg) return gen_with_degrees_alloc(n, d, seed, 0, m, edges, deg, st);
+    if (deg) return gen_with_degrees_alloc(n, d, seed, 0, m, edges, deg, true, st);
     return launch_gen_u32(0, m, d, seed, edges, st);
 }
 
@@ -733,7 +739,7 @@ int ba_generate_ws(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint3
         return BA_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     if ((rc = fill_first_endpoints_whole(n, d, deg, st))) return rc;
-    if (deg) return gen_with_degrees(n, d, seed, 0, m, edges, deg, workspace, workspace_bytes, st);
+    if (deg) return gen_with_degrees(n, d, seed, 0, m, edges, deg, workspace, workspace_bytes, true, st);
     return launch_gen_u32(0, m, d, seed, edges, st);
 }
 
@@ -745,7 +751,7 @@ int ba_generate_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin
     hipStream_t st = (hipStream_t)stream;
     if (deg) {
         if ((rc = launch_first_endpoints<uint32_t>(deg, n, edge_begin, edge_count, d, n, st))) return rc;
-        return gen_with_degrees_alloc(n, d, seed, edge_begin, edge_count, edges, deg, st);
+        return gen_with_degrees_alloc(n, d, seed, edge_begin, edge_count, edges, deg, false, st);
     }
     return launch_gen_u32(edge_begin, edge_count, d, seed, edges, st);
 }
@@ -762,7 +768,8 @@ int ba_generate_range_ws(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_be
     hipStream_t st = (hipStream_t)stream;
     if (deg) {
         if ((rc = launch_first_endpoints<uint32_t>(deg, n, edge_begin, edge_count, d, n, st))) return rc;
-        return gen_with_degrees(n, d, seed, edge_begin, edge_count, edges, deg, workspace, workspace_bytes, st);
+        return gen_with_degrees(n, d, seed, edge_begin, edge_count, edges, deg, workspace, workspace_bytes, false,
+                                st);
     }
     return launch_gen_u32(edge_begin, edge_count, d, seed, edges, st);
 }

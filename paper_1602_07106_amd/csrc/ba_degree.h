@@ -25,7 +25,11 @@
 //   H  (k_deg_hist): one block per part streams its regions into an LDS
 //      histogram of 32768 counters and adds the counts to deg (plain
 //      read-modify-write when a sub-bucket is a single part, atomics only for
-//      the few heavy multi-part ones).
+//      the few heavy multi-part ones).  On a whole graph's first pass, where
+//      deg[v] = d, a single part stores d + count without the read, unless a
+//      region overflowed in the pass (a workspace flag).
+//   tail (k_deg_tail): the targets after the last whole chunk, by global
+//      atomics, launched after H so H's direct stores cannot overwrite them.
 //
 // Region capacities come from the mean-field Barabasi-Albert degree law
 // (expected second endpoints of edges [B, B+C) on nodes [a, b)) with slack;
@@ -94,7 +98,7 @@ struct DegPlan {
     uint32_t NBsub, NW, P;
     uint64_t n, C;
     uint64_t A;  // region entries reserved in the layout
-    uint64_t o_V, o_rcap, o_off, o_fill, o_tot, o_parts, o_partoff, o_L, bytes;
+    uint64_t o_V, o_rcap, o_off, o_fill, o_tot, o_parts, o_partoff, o_flag, o_L, bytes;
 };
 
 static inline uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
@@ -119,6 +123,7 @@ static inline DegPlan make_deg_plan(uint64_t n, uint64_t C, uint32_t P)
     p.o_tot = o; o = align256(o + 4ull * p.NBsub);
     p.o_parts = o; o = align256(o + 4ull * p.NBsub);
     p.o_partoff = o; o = align256(o + 4ull * (p.NBsub + 1));
+    p.o_flag = o; o = align256(o + 4);
     p.o_L = o; o = align256(o + 2 * p.A);
     p.bytes = o;
     return p;
@@ -131,6 +136,7 @@ struct DegArgs {
     unsigned char *ws;
     uint32_t g0;            // first sub-bucket of the window (partition kernel)
     double scale;           // capacity scale (1 normally)
+    uint32_t fresh;         // deg[v] = d for every node and nothing of this pass added yet
 };
 
 __device__ __forceinline__ const uint32_t *ws_V(const DegArgs &a) { return (const uint32_t *)(a.ws + a.p.o_V); }
@@ -138,6 +144,8 @@ __device__ __forceinline__ uint32_t *ws_rcap(const DegArgs &a) { return (uint32_
 __device__ __forceinline__ uint64_t *ws_off(const DegArgs &a) { return (uint64_t *)(a.ws + a.p.o_off); }
 __device__ __forceinline__ uint32_t *ws_fill(const DegArgs &a) { return (uint32_t *)(a.ws + a.p.o_fill); }
 __device__ __forceinline__ uint32_t *ws_tot(const DegArgs &a) { return (uint32_t *)(a.ws + a.p.o_tot); }
+// set when a region overflowed in this pass (its entries went to deg by atomics)
+__device__ __forceinline__ uint32_t *ws_flag(const DegArgs &a) { return (uint32_t *)(a.ws + a.p.o_flag); }
 __device__ __forceinline__ uint32_t *ws_parts(const DegArgs &a) { return (uint32_t *)(a.ws + a.p.o_parts); }
 __device__ __forceinline__ uint32_t *ws_partoff(const DegArgs &a) { return (uint32_t *)(a.ws + a.p.o_partoff); }
 __device__ __forceinline__ uint16_t *ws_L(const DegArgs &a) { return (uint16_t *)(a.ws + a.p.o_L); }
@@ -188,6 +196,7 @@ __global__ __launch_bounds__(1024) void k_deg_plan(DegArgs a)
     uint32_t *rcap = ws_rcap(a);
     uint64_t *off = ws_off(a);
     uint64_t carry = 0;
+    if (threadIdx.x == 0) *ws_flag(a) = 0;
     for (uint32_t i0 = 0; i0 < N; i0 += 1024) {
         const uint32_t g = i0 + threadIdx.x;
         uint64_t x = 0;
@@ -331,6 +340,7 @@ __global__ __launch_bounds__(kPBlock) void k_deg_part(DegArgs a)
                 for (uint32_t u = 0; u < 4; u++)
                     if (x0 + u * kPBlock < total) Lw[t[u].x + x0 + u * kPBlock] = (uint16_t)(w[u] & (kSub - 1));
             } else {
+                if (x0 == threadIdx.x && threadIdx.x == 0) *ws_flag(a) = 1;  // deg takes atomics before H
 #pragma unroll
                 for (uint32_t u = 0; u < 4; u++) {
                     const uint32_t x = x0 + u * kPBlock;
@@ -463,6 +473,9 @@ __global__ __launch_bounds__(kHBlock) void k_deg_hist(DegArgs a)
     }
     __syncthreads();
     const uint64_t vbase = (uint64_t)g << kS2;
+    // deg[v] = d before this block for a single-part sub-bucket of a fresh
+    // pass with no region overflow (the tail's atomics run after this kernel)
+    const bool direct = a.fresh && *ws_flag(a) == 0;
     static_assert(kSub % (8 * kHBlock) == 0, "count write-back batches");
     for (uint32_t y0 = threadIdx.x; y0 < kSub; y0 += 8 * kHBlock) {
         uint32_t c[8];
@@ -471,7 +484,11 @@ __global__ __launch_bounds__(kHBlock) void k_deg_hist(DegArgs a)
             const uint64_t v = vbase + y0 + u * kHBlock;
             c[u] = v < a.p.n ? cnt[y0 + u * kHBlock] : 0u;
         }
-        if (np == 1) {  // the only block of this sub-bucket: plain read-modify-write, 8 reads in flight
+        if (np == 1 && direct) {  // the only block of this sub-bucket: d + count, no read
+#pragma unroll
+            for (uint32_t u = 0; u < 8; u++)
+                if (c[u]) a.deg[vbase + y0 + u * kHBlock] = (uint32_t)a.d + c[u];
+        } else if (np == 1) {  // the only block of this sub-bucket: plain read-modify-write, 8 reads in flight
             uint32_t old[8];
 #pragma unroll
             for (uint32_t u = 0; u < 8; u++) old[u] = c[u] ? a.deg[vbase + y0 + u * kHBlock] : 0u;

@@ -268,6 +268,13 @@ def test_degrees_in_several_passes_with_heavy_sub_buckets():
     edges, deg2 = ba.generate(n, d, seed, degrees=True)
     torch.cuda.synchronize()
     assert np.array_equal(_u32(deg2).astype(np.uint64), ref)
+    # the whole graph through the same small workspace: the first pass stores
+    # single-part counts directly over the filled first endpoints, the other
+    # 31 read-modify-write
+    edges, deg3 = ba.generate(n, d, seed, degrees=True, ws=ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(_u32(edges), E)
+    assert np.array_equal(_u32(deg3).astype(np.uint64), ref)
 
 
 def test_extreme_parameters_sampled():
