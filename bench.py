@@ -13,7 +13,9 @@ Every kernel of a step is timed live with HIP events on the stream it runs
 on (the library's timing hook); `roofline` is that of the kernel with the
 largest share of the step, `kernels` gives every kernel's share and roofline
 fraction.  `cpu_baseline` times the CPU oracle (sequential Batagelj-Brandes
-plus the degree count) on a bounded prefix of the same graph.
+plus the degree count) on a bounded prefix of the same graph;
+`cpu_recompute` times the oracle's per-edge recomputation on every granted
+host core (the paper's own parallel method on the CPU), edges only.
 """
 from __future__ import annotations
 
@@ -97,6 +99,34 @@ def cpu_baseline():
         "cores": 1,
         "kind": "oracle",
         "sample": "first 2^29 edges (n=2^25, d=16, seed=7): sequential Batagelj-Brandes + degree count, %.1f s" % dt,
+    }
+
+
+def cpu_recompute_threads():
+    """A second CPU figure: the paper's own parallel method on the host.  The
+    oracle's per-edge recomputation (no edge array read) runs on disjoint
+    edge ranges in one thread per host core granted (at most 16), on the
+    first 2^29 edges of the headline graph; edges only."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    total, piece = 1 << 29, 1 << 22
+    oracle.lib()
+
+    def work(b):
+        oracle.edges_range(D, SEED, b, piece)  # the foreign call releases the GIL
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(work, range(0, total, piece)))
+    dt = time.perf_counter() - t0
+    return {
+        "value": total / dt,
+        "unit": "edges/s",
+        "cores": threads,
+        "kind": "oracle per-edge recomputation, one thread per core over disjoint edge ranges (edges only)",
+        "sample": "first 2^29 edges (n=2^26, d=16, seed=7) in pieces of 2^22, %.1f s" % dt,
     }
 
 
@@ -608,6 +638,7 @@ def main() -> int:
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
+        line["cpu_recompute"] = cpu_recompute_threads()
     print(json.dumps(line), flush=True)
     return 0
 
