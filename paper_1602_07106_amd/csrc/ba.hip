@@ -157,21 +157,21 @@ __device__ __forceinline__ void chain_tile_visit(uint32_t tn, uint32_t lane, R r
             next += (uint32_t)__popcll(dm);
         }
     }
-    // tail: at most 64 chains in flight, no more than tn - next left to claim
-    bool active = li < tn;
-    uint64_t live = __ballot(active);
+    // tail: at most 64 chains in flight, no more than tn - next left to claim.
+    // A lane is live iff li < tn; the masks come from ballots of plain
+    // compares (a ballot of a combined condition costs two more instructions).
+    uint64_t live = __ballot(li < tn);
     while (live) {
         r = hash(r);
-        const bool done = active && stop(r);
-        const uint64_t dm = __ballot(done);
-        if (done) {
+        const bool fin = stop(r);
+        const uint64_t dm = __ballot(fin) & live;
+        if (fin && li < tn) {
             visit(li, r);
             li = next + lane_rank(dm);
-            active = li < tn;
             r = rbase + 2 * (R)li;
         }
         next += (uint32_t)__popcll(dm);
-        live = __ballot(active);
+        live = __ballot(li < tn);
     }
 }
 
