@@ -90,7 +90,8 @@ __device__ __forceinline__ uint64_t fdiv64(uint64_t x, const Divider &v)
 }
 
 // Edge pair j, j+1 of a tile from the stage: u = floor(i/d) and v (the
-// stage holds floor(r/2) on the narrow path, v itself on the wide path).
+// stage holds the final position r on the narrow path, v itself on the wide
+// path).
 template <bool NARROW, bool POW2>
 __device__ __forceinline__ void flush_pair(const GenArgs &a, const uint32_t *stage, uint64_t ibase, uint32_t j,
                                            uint32_t &u0, uint32_t &u1, uint32_t &v0, uint32_t &v1)
@@ -100,8 +101,8 @@ __device__ __forceinline__ void flush_pair(const GenArgs &a, const uint32_t *sta
         const uint32_t i0 = (uint32_t)ibase + j;
         u0 = fdiv32<POW2>(i0, a.div);
         u1 = fdiv32<POW2>(i0 + 1, a.div);
-        v0 = fdiv32<POW2>(s.x, a.div);
-        v1 = fdiv32<POW2>(s.y, a.div);
+        v0 = fdiv32<POW2>(s.x >> 1, a.div);
+        v1 = fdiv32<POW2>(s.y >> 1, a.div);
     } else {
         const uint64_t i0 = ibase + j;
         u0 = (uint32_t)fdiv64<POW2>(i0, a.div);
@@ -175,12 +176,64 @@ __device__ __forceinline__ void chain_tile_visit(uint32_t tn, uint32_t lane, R r
     }
 }
 
-// The chain loop writing out(r) of edge li to stage[li].
+// A wave-uniform value kept opaque to the compiler, so that an expression
+// built on it is not reassociated into one that needs per-lane work first.
+// (readfirstlane returns int: each half goes through uint32_t, so the low
+// half is not sign-extended into the high one)
+__device__ __forceinline__ uint32_t wave_uniform(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t wave_uniform(uint64_t x)
+{
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+// The chain loop writing out(r) of edge li to stage[li].  The same refill
+// as chain_tile_visit, but a lane keeps the LDS byte address of its stage
+// slot instead of li: a finishing lane's next slot and restart position are
+// each one multiply-add of its rank onto a wave-uniform base (the slot and
+// position of edge `next`), where going through li costs more instructions
+// on every step.
 template <class R, class H, class S, class O>
 __device__ __forceinline__ void chain_tile_until(uint32_t *stage, uint32_t tn, uint32_t lane, R rbase, H hash,
                                                  S stop, O out)
 {
-    chain_tile_visit(tn, lane, rbase, hash, stop, [&](uint32_t li, R r) { stage[li] = out(r); });
+    tn = __builtin_amdgcn_readfirstlane(tn);  // wave-uniform: keeps loop control scalar
+    const uint32_t sbase = wave_uniform((uint32_t)(uintptr_t)(lds_u32 *)stage);  // LDS byte address
+    uint32_t sa = sbase + 4 * lane;
+    uint32_t next = kWave;  // next unclaimed edge (wave-uniform)
+    R r = rbase + 2 * (R)lane;
+    if (tn >= kWave) {
+        while (next + kWave <= tn) {
+            r = hash(r);
+            const bool fin = stop(r);
+            const uint64_t dm = __ballot(fin);
+            if (fin) {
+                *(lds_u32 *)(uintptr_t)sa = out(r);
+                const uint32_t k = lane_rank(dm);
+                sa = wave_uniform(sbase + 4 * next) + 4 * k;
+                r = wave_uniform((R)(rbase + 2 * (R)next)) + 2 * (R)k;
+            }
+            next += (uint32_t)__popcll(dm);
+        }
+    }
+    // tail, as in chain_tile_visit: live iff li < tn
+    uint32_t li = (sa - sbase) >> 2;
+    uint64_t live = __ballot(li < tn);
+    while (live) {
+        r = hash(r);
+        const bool fin = stop(r);
+        const uint64_t dm = __ballot(fin) & live;
+        if (fin && li < tn) {
+            stage[li] = out(r);
+            li = next + lane_rank(dm);
+            r = rbase + 2 * (R)li;
+        }
+        next += (uint32_t)__popcll(dm);
+        live = __ballot(li < tn);
+    }
 }
 
 // The plain model: chains end at the first even position.
@@ -197,7 +250,7 @@ __global__ __launch_bounds__(kGenBlock) void k_gen_u32(GenArgs a)
 {
     __shared__ uint32_t stage_all[kGenWaves][kTile];
     const uint32_t lane = __lane_id();
-    const uint32_t wv = threadIdx.x / kWave;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform: scalar tile bases
     uint32_t *stage = stage_all[wv];
     const uint64_t wstride = (uint64_t)gridDim.x * kGenWaves;
 
@@ -208,7 +261,7 @@ __global__ __launch_bounds__(kGenBlock) void k_gen_u32(GenArgs a)
 
         if constexpr (NARROW)
             chain_tile(stage, tn, lane, (uint32_t)(2 * ibase + 1), [&](uint32_t r) { return hash_narrow(r, a.key); },
-                       [](uint32_t r) { return r >> 1; });
+                       [](uint32_t r) { return r; });
         else
             chain_tile(stage, tn, lane, 2 * ibase + 1, [&](uint64_t r) { return hash_wide(r, a.key); },
                        [&](uint64_t r) { return (uint32_t)div64(r >> 1, a.div); });
