@@ -68,7 +68,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_gen_batch(BatchArgs a)
         const uint32_t tn = (uint32_t)min((uint64_t)TILE, I.m - off);
         if (I.narrow)
             chain_tile(stage, tn, lane, (uint32_t)(2 * off + 1), [&](uint32_t r) { return hash_narrow(r, I.key); },
-                       [](uint32_t r) { return r >> 1; });
+                       [](uint32_t r) { return r; });  // the final position; the flush divides
         else
             chain_tile(stage, tn, lane, 2 * off + 1, [&](uint64_t r) { return hash_wide(r, I.key); },
                        [&](uint64_t r) { return (uint32_t)div64(r >> 1, I.div); });
@@ -90,8 +90,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_gen_batch(BatchArgs a)
                     const uint32_t i0 = (uint32_t)off + jj;
                     u0 = fdiv32<P>(i0, I.div);
                     u1 = fdiv32<P>(i0 + 1, I.div);
-                    v0 = fdiv32<P>(s.x, I.div);
-                    v1 = fdiv32<P>(s.y, I.div);
+                    v0 = fdiv32<P>(s.x >> 1, I.div);
+                    v1 = fdiv32<P>(s.y >> 1, I.div);
                 } else {
                     const uint64_t i0 = off + jj;
                     u0 = (uint32_t)fdiv64<P>(i0, I.div);
