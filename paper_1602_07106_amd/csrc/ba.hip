@@ -188,6 +188,50 @@ __device__ __forceinline__ uint64_t wave_uniform(uint64_t x)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// The same refill as chain_tile_visit for consumers that need the edge's
+// start position 2i+1 rather than its index in the run: visit(r0, r) gets the
+// lane's start position r0 and its final position r.  A finishing lane's
+// next start position is one multiply-add of its rank onto a wave-uniform
+// base, and the consumer gets i = r0 >> 1 and the checksum multiplier 2i+1 =
+// r0 without recomputing them from li.
+template <class R, class H, class S, class V>
+__device__ __forceinline__ void chain_run_visit(uint32_t tn, uint32_t lane, R rbase, H hash, S stop, V visit)
+{
+    tn = __builtin_amdgcn_readfirstlane(tn);  // wave-uniform: keeps loop control scalar
+    uint32_t next = kWave;                    // next unclaimed edge (wave-uniform)
+    R r0 = rbase + 2 * (R)lane;
+    R r = r0;
+    if (tn >= kWave) {
+        while (next + kWave <= tn) {
+            r = hash(r);
+            const bool fin = stop(r);
+            const uint64_t dm = __ballot(fin);
+            if (fin) {
+                visit(r0, r);
+                r0 = wave_uniform((R)(rbase + 2 * (R)next)) + 2 * (R)lane_rank(dm);
+                r = r0;
+            }
+            next += (uint32_t)__popcll(dm);
+        }
+    }
+    // tail: live iff li < tn
+    uint32_t li = (uint32_t)((r0 - rbase) >> 1);
+    uint64_t live = __ballot(li < tn);
+    while (live) {
+        r = hash(r);
+        const bool fin = stop(r);
+        const uint64_t dm = __ballot(fin) & live;
+        if (fin && li < tn) {
+            visit(r0, r);
+            li = next + lane_rank(dm);
+            r0 = rbase + 2 * (R)li;
+            r = r0;
+        }
+        next += (uint32_t)__popcll(dm);
+        live = __ballot(li < tn);
+    }
+}
+
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
 // The chain loop writing out(r) of edge li to stage[li].  The same refill

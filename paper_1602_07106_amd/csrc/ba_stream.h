@@ -55,6 +55,14 @@ __device__ __forceinline__ uint64_t sdiv64(uint64_t x, const Divider &v)
     return (t + ((x - t) >> 1)) >> v.shift;
 }
 
+// floor(x / 2d): a power-of-two d takes one 64-bit shift (shift + 1 <= 32)
+template <bool POW2>
+__device__ __forceinline__ uint64_t shalf64(uint64_t x, const Divider &v)
+{
+    if constexpr (POW2) return x >> (v.shift + 1);
+    return sdiv64<false>(x >> 1, v);
+}
+
 template <bool NARROW, bool POW2>
 __global__ __launch_bounds__(kStreamBlock) void k_stream(StreamArgs a)
 {
@@ -73,22 +81,27 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream(StreamArgs a)
         // per_wave < 2^32: the host splits larger launches
         const uint32_t tn = (uint32_t)min(a.per_wave, a.count - w0);
         const uint64_t ibase = a.begin + w0;
-        chain_tile_visit(
+        chain_run_visit(
             tn, lane, (R)(2 * ibase + 1),
             [&](R r) -> R {
                 if constexpr (NARROW) return hash_narrow(r, a.key);
                 else return hash_wide(r, a.key);
             },
             [](R r) { return !((uint32_t)r & 1u); },
-            [&](uint32_t li, R r) {
-                const uint64_t i = ibase + li;
-                const uint64_t v = NARROW ? (uint64_t)sdiv32<POW2>((uint32_t)(r >> 1), a.div) : sdiv64<POW2>(r >> 1, a.div);
-                const uint64_t u = NARROW ? (uint64_t)sdiv32<POW2>((uint32_t)i, a.div) : sdiv64<POW2>(i, a.div);
+            [&](R r0, R r) {  // r0 = 2i + 1, the edge's start position
+                uint64_t u, v;
+                if constexpr (NARROW) {
+                    v = sdiv32<POW2>((uint32_t)r >> 1, a.div);
+                    u = sdiv32<POW2>((uint32_t)r0 >> 1, a.div);
+                } else {
+                    v = shalf64<POW2>(r, a.div);
+                    u = shalf64<POW2>(r0, a.div);
+                }
                 if (v < a.klds)
                     atomicAdd(&cnt[v], 1u);
                 else if (v < a.k)
                     __hip_atomic_fetch_add(a.deg + v, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                xs ^= ((u << 32) + v) * (2 * i + 1);
+                xs ^= ((u << 32) + v) * (uint64_t)r0;
             });
     }
     if (a.cs) {
