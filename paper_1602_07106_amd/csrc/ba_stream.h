@@ -173,10 +173,17 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
         if constexpr (NARROW) return hash_narrow(r, a.key);
         else return hash_wide(r, a.key);
     };
-    auto finish = [&](uint32_t li, R r, uint32_t &pend_old, uint32_t &pend_v) {
-        const uint64_t i = ibase + li;
-        const uint64_t v = NARROW ? (uint64_t)sdiv32<POW2>((uint32_t)(r >> 1), a.div) : sdiv64<POW2>(r >> 1, a.div);
-        const uint64_t u = NARROW ? (uint64_t)sdiv32<POW2>((uint32_t)i, a.div) : sdiv64<POW2>(i, a.div);
+    // r0 = 2i + 1: the edge's start position (i = r0 >> 1, and the checksum
+    // multiplier itself)
+    auto finish = [&](R r0, R r, uint32_t &pend_old, uint32_t &pend_v) {
+        uint64_t u, v;
+        if constexpr (NARROW) {
+            v = sdiv32<POW2>((uint32_t)r >> 1, a.div);
+            u = sdiv32<POW2>((uint32_t)r0 >> 1, a.div);
+        } else {
+            v = shalf64<POW2>(r, a.div);
+            u = shalf64<POW2>(r0, a.div);
+        }
         settle(pend_old, pend_v);
         if (v < ktier) {
             pend_old = atomicAdd(&cnt[(uint32_t)v >> 1], 1u << (((uint32_t)v & 1u) << 4));
@@ -184,7 +191,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
         } else if (v < a.k) {
             __hip_atomic_fetch_add(a.deg + v, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        xs ^= ((u << 32) + v) * (2 * i + 1);
+        xs ^= ((u << 32) + v) * (uint64_t)r0;
     };
 
     // Every lane runs two chains (A and B): their hash evaluations are
@@ -194,7 +201,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
     // tot stay idle).  Up to 128 edges finish per step, so a wave finishes
     // at most kStreamRoundClaims + 127 edges between two barriers.
     uint32_t pa_old = 0, pa_v = kNone, pb_old = 0, pb_v = kNone;
-    uint32_t la = lane, lb = lane + kWave, claimed = 2 * kWave, next_bar = 2 * kWave + kStreamRoundClaims;
+    uint32_t claimed = 2 * kWave, next_bar = 2 * kWave + kStreamRoundClaims;
     uint64_t bars = 0;
     auto round_edge = [&]() {
         if (claimed >= next_bar) {
@@ -205,7 +212,10 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
             next_bar += kStreamRoundClaims;
         }
     };
-    R ra = rbase + 2 * (R)la, rb = rbase + 2 * (R)lb;
+    // start positions of the lane's two edges (edge index li = (r0 - rbase) / 2);
+    // a refill is one multiply-add of the rank onto a wave-uniform base
+    R ra0 = rbase + 2 * (R)lane, rb0 = rbase + 2 * (R)(lane + kWave);
+    R ra = ra0, rb = rb0;
     if (tot >= 2 * kWave) {
         while (claimed + 2 * kWave <= tot) {  // every lane holds two live edges
             ra = hash(ra);
@@ -213,20 +223,21 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
             const bool fa = !((uint32_t)ra & 1u), fb = !((uint32_t)rb & 1u);
             const uint64_t ma = __ballot(fa), mb = __ballot(fb);
             if (fa) {
-                finish(la, ra, pa_old, pa_v);
-                la = claimed + lane_rank(ma);
-                ra = rbase + 2 * (R)la;
+                finish(ra0, ra, pa_old, pa_v);
+                ra0 = wave_uniform((R)(rbase + 2 * (R)claimed)) + 2 * (R)lane_rank(ma);
+                ra = ra0;
             }
             claimed += (uint32_t)__popcll(ma);
             if (fb) {
-                finish(lb, rb, pb_old, pb_v);
-                lb = claimed + lane_rank(mb);
-                rb = rbase + 2 * (R)lb;
+                finish(rb0, rb, pb_old, pb_v);
+                rb0 = wave_uniform((R)(rbase + 2 * (R)claimed)) + 2 * (R)lane_rank(mb);
+                rb = rb0;
             }
             claimed += (uint32_t)__popcll(mb);
             round_edge();
         }
     }
+    uint32_t la = (uint32_t)((ra0 - rbase) >> 1), lb = (uint32_t)((rb0 - rbase) >> 1);
     bool aa = la < tot, ab = lb < tot;
     uint64_t live = __ballot(aa || ab);
     while (live) {
@@ -235,17 +246,19 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
         const bool fa = aa && !((uint32_t)ra & 1u), fb = ab && !((uint32_t)rb & 1u);
         const uint64_t ma = __ballot(fa), mb = __ballot(fb);
         if (fa) {
-            finish(la, ra, pa_old, pa_v);
+            finish(ra0, ra, pa_old, pa_v);
             la = claimed + lane_rank(ma);
             aa = la < tot;
-            ra = rbase + 2 * (R)la;
+            ra0 = rbase + 2 * (R)la;
+            ra = ra0;
         }
         claimed += (uint32_t)__popcll(ma);
         if (fb) {
-            finish(lb, rb, pb_old, pb_v);
+            finish(rb0, rb, pb_old, pb_v);
             lb = claimed + lane_rank(mb);
             ab = lb < tot;
-            rb = rbase + 2 * (R)lb;
+            rb0 = rbase + 2 * (R)lb;
+            rb = rb0;
         }
         claimed += (uint32_t)__popcll(mb);
         round_edge();
