@@ -72,13 +72,14 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
 
 
 // floor(x / d) with the divider's kind (a power of two or not) fixed at
-// compile time, so the flush loops carry no per-step branch on it.
+// compile time, so the flush loops carry no per-step branch on it.  x < 2^31
+// (the 31-bit multiplier); values of a pair past the end of a tile may break
+// that, and they are never stored.
 template <bool POW2>
 __device__ __forceinline__ uint32_t fdiv32(uint32_t x, const Divider &v)
 {
     if constexpr (POW2) return x >> v.shift;
-    const uint32_t t = mulhi32(x, v.m32);
-    return (t + ((x - t) >> 1)) >> v.shift;
+    return mulhi32(x, v.m32) >> v.shift;
 }
 
 template <bool POW2>
@@ -1304,7 +1305,7 @@ int ba_host_divide(uint32_t d, const uint64_t *x, uint64_t *q, uint64_t count)
     if (d == 0 || (count && (!x || !q))) return BA_EINVAL;
     const Divider v = make_divider(d);
     for (uint64_t j = 0; j < count; j++)
-        q[j] = (x[j] >> 32) ? div64(x[j], v) : (uint64_t)div32((uint32_t)x[j], v);
+        q[j] = (x[j] >> 31) ? div64(x[j], v) : (uint64_t)div32((uint32_t)x[j], v);
     return BA_OK;
 }
 

@@ -38,13 +38,12 @@ struct StreamArgs {
 
 // floor(x / d) with the divider's kind fixed at compile time (the streaming
 // kernels divide on every finished edge; d is a power of two when POW2),
-// otherwise the same Granlund-Montgomery step as div32 / div64.
+// otherwise the same multiply-high steps as div32 (x < 2^31) / div64.
 template <bool POW2>
 __device__ __forceinline__ uint32_t sdiv32(uint32_t x, const Divider &v)
 {
     if constexpr (POW2) return x >> v.shift;
-    const uint32_t t = mulhi32(x, v.m32);
-    return (t + ((x - t) >> 1)) >> v.shift;
+    return mulhi32(x, v.m32) >> v.shift;
 }
 
 template <bool POW2>
