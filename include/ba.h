@@ -338,10 +338,11 @@ int ba_last_hip_error(void);
 /*
  * Host-side self-test of the exact division by d the kernels use for
  * floor(i/d) and floor(r/(2d)) (multiply-high method of Granlund & Montgomery,
- * PLDI 1994): x < 2^31 takes the 31-bit-numerator form with a 32-bit
- * multiplier, larger x the 64-bit form.  Writes q[j] = floor(x[j] / d)
- * computed that way, on the host, for count host values.  d >= 1.  Returns
- * BA_OK or BA_EINVAL.
+ * PLDI 1994, the round-up form for numerators one bit narrower than the
+ * word): x < 2^31 takes the 32-bit form, x < 2^63 the 64-bit form, and
+ * x >= 2^63 (never a kernel numerator) is divided plainly.  Writes
+ * q[j] = floor(x[j] / d) computed that way, on the host, for count host
+ * values.  d >= 1.  Returns BA_OK or BA_EINVAL.
  */
 int ba_host_divide(uint32_t d, const uint64_t *x, uint64_t *q, uint64_t count);
 

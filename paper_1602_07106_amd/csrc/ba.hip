@@ -86,8 +86,7 @@ template <bool POW2>
 __device__ __forceinline__ uint64_t fdiv64(uint64_t x, const Divider &v)
 {
     if constexpr (POW2) return x >> v.shift;
-    const uint64_t t = mulhi64(x, v.m64);
-    return (t + ((x - t) >> 1)) >> v.shift;
+    return mulhi64(x, v.m64) >> v.shift;  // x < 2^63
 }
 
 // Edge pair j, j+1 of a tile from the stage: u = floor(i/d) and v (the
@@ -1305,7 +1304,7 @@ int ba_host_divide(uint32_t d, const uint64_t *x, uint64_t *q, uint64_t count)
     if (d == 0 || (count && (!x || !q))) return BA_EINVAL;
     const Divider v = make_divider(d);
     for (uint64_t j = 0; j < count; j++)
-        q[j] = (x[j] >> 31) ? div64(x[j], v) : (uint64_t)div32((uint32_t)x[j], v);
+        q[j] = (x[j] >> 63) ? x[j] / d : (x[j] >> 31) ? div64(x[j], v) : (uint64_t)div32((uint32_t)x[j], v);
     return BA_OK;
 }
 

@@ -107,22 +107,21 @@ __device__ __forceinline__ uint64_t hash_wide(uint64_t r, const HashKey &k) { re
 
 // Exact floor(x / d) for a fixed d >= 1 (Granlund & Montgomery, "Division by
 // invariant integers using multiplication", PLDI 1994), with l = ceil(log2 d)
-// for d not a power of 2 (a power of two is a plain shift by log2 d):
-//  * 64-bit x, the round-up method with an N+1-bit multiplier:
-//      m' = floor(2^64 * (2^l - d) / d) + 1,  t = mulhi(m', x),
-//      floor(x / d) = (t + ((x - t) >> 1)) >> (l - 1);
-//  * x < 2^31 (every 32-bit quotient the kernels take: edge indices and
-//    halved positions below 2^32), the round-up method for 31-bit
-//    numerators, whose multiplier fits 32 bits:
-//      m = floor(2^(31+l) / d) + 1 < 2^32,  floor(x / d) = mulhi(m, x) >> (l - 1).
-//    With e = m*d - 2^(31+l) in (0, d], x*m / 2^(31+l) = x/d + x*e / (d 2^(31+l))
-//    and the second term is below 2^-l < 1/d, so the floor does not move.
+// for d not a power of 2 (a power of two is a plain shift by log2 d).  Every
+// quotient the kernels take has a numerator one bit narrower than its word
+// (edge indices and halved positions: below 2^31 when positions are below
+// 2^32, below 2^63 always), so both widths use the round-up method for
+// (N-1)-bit numerators, whose multiplier fits N bits:
+//      m = floor(2^(N-1+l) / d) + 1 < 2^N,  floor(x / d) = mulhi(m, x) >> (l - 1)
+// for x < 2^(N-1).  With e = m*d - 2^(N-1+l) in (0, d],
+// x*m / 2^(N-1+l) = x/d + x*e / (d 2^(N-1+l)), and the second term is below
+// 2^-l < 1/d, so the floor does not move.
 struct Divider {
     uint32_t d;
     uint32_t pow2;   // 1 if d is a power of two
     uint32_t shift;  // log2 d (pow2) or l - 1
-    uint32_t m32;    // m for 31-bit numerators
-    uint64_t m64;    // m' for 64-bit numerators
+    uint32_t m32;    // m for N = 32 (x < 2^31)
+    uint64_t m64;    // m for N = 64 (x < 2^63)
 };
 
 inline Divider make_divider(uint32_t d)
@@ -138,8 +137,7 @@ inline Divider make_divider(uint32_t d)
     uint32_t l = 32 - (uint32_t)__builtin_clz(d - 1);  // ceil(log2 d), d >= 3
     v.shift = l - 1;
     v.m32 = (uint32_t)((((uint64_t)1 << (31 + l)) / d) + 1);
-    unsigned __int128 num = ((unsigned __int128)1 << 64) * (((unsigned __int128)1 << l) - d);
-    v.m64 = (uint64_t)(num / d + 1);
+    v.m64 = (uint64_t)((((unsigned __int128)1 << (63 + l)) / d) + 1);
     return v;
 }
 
@@ -164,11 +162,11 @@ __host__ __device__ __forceinline__ uint32_t div32(uint32_t x, const Divider &v)
     return mulhi32(x, v.m32) >> v.shift;
 }
 
+// x < 2^63
 __host__ __device__ __forceinline__ uint64_t div64(uint64_t x, const Divider &v)
 {
     if (v.pow2) return x >> v.shift;
-    uint64_t t = mulhi64(x, v.m64);
-    return (t + ((x - t) >> 1)) >> v.shift;
+    return mulhi64(x, v.m64) >> v.shift;
 }
 
 }  // namespace ba

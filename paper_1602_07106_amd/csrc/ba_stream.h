@@ -50,8 +50,7 @@ template <bool POW2>
 __device__ __forceinline__ uint64_t sdiv64(uint64_t x, const Divider &v)
 {
     if constexpr (POW2) return x >> v.shift;
-    const uint64_t t = mulhi64(x, v.m64);
-    return (t + ((x - t) >> 1)) >> v.shift;
+    return mulhi64(x, v.m64) >> v.shift;  // x < 2^63
 }
 
 // floor(x / 2d): a power-of-two d takes one 64-bit shift (shift + 1 <= 32)

@@ -49,7 +49,7 @@ def _boundary_values(d):
     M = (1 << 64) - 1
     vals = {0, 1, 2, d - 1, d, d + 1, 2 * d - 1, 2 * d, (1 << 31) - 1, 1 << 31, (1 << 32) - 1, 1 << 32,
             (1 << 32) + 1, (1 << 37) - 1, (1 << 63) - 1, 1 << 63, M - 1, M}
-    for k in [1, 2, 3, 1000, (1 << 31) // d, (1 << 32) // d, M // d]:  # top of the 31-bit form too
+    for k in [1, 2, 3, 1000, (1 << 31) // d, (1 << 32) // d, (1 << 63) // d, M // d]:  # tops of both forms
         for delta in (-1, 0, 1):
             vals.add(k * d + delta)
     return sorted(v for v in vals if 0 <= v <= M)
@@ -65,7 +65,7 @@ def test_exact_division_random():
     rng = random.Random(5)
     for _ in range(200):
         d = rng.randint(1, (1 << 32) - 1) if rng.random() < 0.5 else rng.randint(1, 200)
-        xs = [rng.getrandbits(rng.choice([16, 30, 31, 31, 32, 33, 40, 64])) for _ in range(200)]
+        xs = [rng.getrandbits(rng.choice([16, 30, 31, 31, 32, 33, 40, 62, 63, 63, 64])) for _ in range(200)]
         assert _host_divide(d, xs) == [x // d for x in xs]
 
 
