@@ -17,10 +17,10 @@
 // until the tile runs dry.
 //
 // Output.  The stored kernel writes edge pairs (u, v) as uint32.  Finished
-// chains leave floor(r/2) (narrow path) or v (wide path) in a per-wave LDS
-// tile; when the tile is complete the wave writes it out as 16-byte
-// (two-edge) coalesced stores, computing u = floor(i/d) and v on the way.
-// The degree array (ba_degree.h) is computed from the written edges by a
+// chains leave their final position r (narrow path) or v (wide path) in a
+// per-wave LDS tile; when the tile is complete the wave writes it out as
+// 16-byte (two-edge) coalesced stores, computing u = floor(i/d) and v on the
+// way.  The degree array (ba_degree.h) is computed from the target list by a
 // radix partition and LDS histograms; first endpoints contribute exactly d
 // per node, in closed form.
 //
