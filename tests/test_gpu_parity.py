@@ -280,9 +280,11 @@ def test_degrees_in_several_passes_with_heavy_sub_buckets():
 def test_extreme_parameters_sampled():
     # the largest uint32 graph (IDs up to 2^32 - 1), a huge d (one divisor
     # for 2^31 - 1 edges per node), d = 1 with 64-bit positions, extreme seeds
-    # d = 2^31 with n = 1: the largest power-of-two divisor on 32-bit positions
+    # d = 2^31 with n = 1: the largest power-of-two divisor on 32-bit positions;
+    # n = 3, d = 715827882: a large odd-factor divisor with edge indices up to
+    # 2^31 - 3 on 32-bit positions (the 31-bit-numerator division)
     cases = [((1 << 32), 2, 5), ((1 << 32), 1, M64), (3, (1 << 31) - 1, 0), (5, (1 << 30) + 7, 77),
-             ((1 << 33) + 3, 1, 9), (1, 1 << 31, 3)]
+             ((1 << 33) + 3, 1, 9), (1, 1 << 31, 3), (3, 715827882, 11)]
     for n, d, seed in cases:
         m = n * d
         for b in [0, m // 2 - 1000, m - 2000]:
