@@ -1,6 +1,7 @@
 """The pins must catch plausible mistakes: plant each one in a private copy of
 the oracle's C source (on the CPU), rebuild it, and check that some pin from
-test_oracle_hash / test_oracle_model fails against the planted copy."""
+test_oracle_hash, test_oracle_model, test_oracle_model_ext or
+test_oracle_checksum fails against the planted copy."""
 import ctypes
 import os
 import subprocess
@@ -9,6 +10,7 @@ import tempfile
 import pytest
 
 import oracle
+from tests import test_oracle_checksum as tc
 from tests import test_oracle_hash as th
 from tests import test_oracle_model as tm
 from tests import test_oracle_model_ext as tx
@@ -26,6 +28,10 @@ MUTANTS = [
     ("bb_oracle.c", "second endpoint r/d", "*v = r / (2 * d);", "*v = r / d;"),
     ("bb_oracle.c", "chain start", "uint64_t r = 2 * i + 1;\n    uint64_t k = 0;", "uint64_t r = 2 * i + 3;\n    uint64_t k = 0;"),
     ("bb_oracle.c", "stream counts u twice", "if (u < k) deg_k[u] += 1;", "if (u < k) deg_k[u] += 2;"),
+    ("bb_oracle.c", "checksum multiplier dropped", "return ((u << 32) + v) * (2 * i + 1);", "return ((u << 32) + v);"),
+    ("bb_oracle.c", "checksum multiplier even", "return ((u << 32) + v) * (2 * i + 1);", "return ((u << 32) + v) * (2 * i + 2);"),
+    ("bb_oracle.c", "checksum endpoints swapped", "return ((u << 32) + v) * (2 * i + 1);", "return ((v << 32) + u) * (2 * i + 1);"),
+    ("bb_oracle.c", "checksum XOR of a partial range", "*cs ^= x;", "*cs ^= x & ~1ull;"),
     ("bb_model.c", "draw bound with loops r + 1", "if (!(M->flags & BBO_NO_LOOPS)) return r;", "if (!(M->flags & BBO_NO_LOOPS)) return r + 1;"),
     ("bb_model.c", "no-loop bound at the edge, not the node", "return 2 * M->m0 + 2 * M->d * (i / M->d);", "return 2 * M->m0 + 2 * i;"),
     ("bb_model.c", "seed offset m0 instead of 2 m0", "return (uint32_t)(M->n0 + (r - 2 * M->m0) / (2 * M->d));", "return (uint32_t)(M->n0 + (r - M->m0) / (2 * M->d));"),
@@ -43,6 +49,10 @@ def _pins():
     yield lambda: tm.test_literal_python_generate_edge_equals_c_oracle(250, 4, 1)
     yield tm.test_streaming_consumer_agrees_with_stored_array
     yield tm.test_degree_distribution_has_the_barabasi_albert_power_law_tail
+    yield lambda: [tc.test_a_lone_unit_edge_gives_the_position_multiplier(i) for i in (0, 3, 123457)]
+    yield tc.test_word_is_a_bijection_of_the_pair_for_every_position
+    yield tc.test_two_edges_that_exchange_their_targets_change_the_checksum
+    yield tc.test_checksum_is_the_xor_of_any_split_and_repeats_cancel
     yield lambda: [tx.test_crc32c_published_vectors(msg, c) for msg, c in tx._vectors()]
     yield tx.test_h_crc_is_the_papers_hash_crc
     yield lambda: tx.test_empty_seed_graph_with_loops_is_the_plain_model(50, 3, 1)
