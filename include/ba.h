@@ -25,7 +25,12 @@
  *
  * Conventions for every entry point:
  *  - Pointers named as device pointers must be device memory of the current
- *    HIP device, owned by the caller; the library never allocates or frees.
+ *    HIP device, owned by the caller.  The library never allocates or frees
+ *    device memory: what a call needs beyond its outputs comes from a
+ *    caller-owned workspace (the *_ws calls, batches, the server's arena) or
+ *    from the fixed static scratch of ba_generate_static.  Host memory is
+ *    allocated only by ba_batch_upload (a staging copy of the table),
+ *    ba_server_create (pinned staging) and the server's bookkeeping.
  *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls are
  *    asynchronous: outputs are valid once the stream reaches the call.
  *    Execution errors surface at the caller's next synchronisation.
@@ -33,8 +38,11 @@
  *    launched and no output is touched.
  *  - m = 0 (n = 0 or d = 0) is valid; the call then only writes the outputs
  *    that have a defined value (zero degrees, zero checksum).
- *  - Calls on different streams may run concurrently; the library keeps no
- *    mutable state other than a thread-local last HIP error code.
+ *  - Calls on different streams may run concurrently.  Mutable state: a
+ *    thread-local last HIP error code, the thread-local records of the timing
+ *    hook, the per-device tuned shape of the batched kernel (written only by
+ *    ba_batch_autotune, read by ba_batch_launch, atomic) and the static
+ *    scratch of ba_generate_static.
  */
 #ifndef BA_H
 #define BA_H
@@ -48,7 +56,8 @@ extern "C" {
 /* Status codes. */
 #define BA_OK 0
 #define BA_EINVAL (-1)  /* null or misaligned buffer, range past m, first_k > n */
-#define BA_ERANGE (-2)  /* 2*n*d does not fit 64 bits, or node IDs do not fit the output type */
+#define BA_ERANGE (-2)  /* 2*n*d does not fit 64 bits, or IDs or counts do not fit the output type */
+#define BA_ENOMEM (-3)  /* a workspace (or the static scratch) too small for the smallest pass */
 #define BA_EDEVICE (-4) /* a HIP call failed; ba_last_hip_error() gives its hipError_t */
 
 /*
@@ -57,9 +66,15 @@ extern "C" {
  *           edges[2i+1] = E[2i+1].  4-byte aligned (16-byte aligned is faster).
  *   deg   : device, uint32[n] or NULL.  When not NULL it is overwritten with
  *           deg[v] = number of positions p with E[p] = v (a self-loop counts
- *           twice; the degrees sum to 2m).  Computed in the same pass.
- * Errors: BA_ERANGE if n > 2^32 or 2*n*d >= 2^64; BA_EINVAL if a needed
- * pointer is NULL or misaligned.
+ *           twice; the degrees sum to 2m).  Computed in the same pass: the
+ *           first endpoints in closed form (d per node), the second ones by
+ *           global atomics from the generator (no workspace, no allocation;
+ *           about an order of magnitude slower than ba_generate_ws, whose
+ *           partition-and-histogram pipeline is the fast path).
+ * Errors: BA_ERANGE if n > 2^32 or 2*n*d >= 2^64, or deg is given and
+ * n*d + d >= 2^32 (a count could exceed uint32: node v holds at most its d
+ * first endpoints and the second endpoints of edges d*v .. n*d-1);
+ * BA_EINVAL if a needed pointer is NULL or misaligned.
  */
 int ba_generate(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint32_t *deg,
                 void *stream);
@@ -96,16 +111,26 @@ uint64_t ba_generate_workspace_bytes(uint64_t n, uint32_t d, uint64_t edge_count
  *   workspace : device, 256-byte aligned, workspace_bytes long, owned by the
  *               caller; its contents are scratch (not preserved).  Calls that
  *               share a workspace must be ordered (same stream).
- * Without a workspace, ba_generate / ba_generate_range take one from the
- * stream-ordered allocator (hipMallocAsync / hipFreeAsync) when deg != NULL.
  * Errors: as the calls without workspace, plus BA_EINVAL if deg != NULL and
- * the workspace is NULL, misaligned or smaller than a 2^20-edge pass needs.
+ * the workspace is NULL or misaligned, and BA_ENOMEM if it is smaller than
+ * the smallest pass (2^20 edges) needs.
  */
 int ba_generate_ws(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint32_t *deg,
                    void *workspace, uint64_t workspace_bytes, void *stream);
 int ba_generate_range_ws(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin,
                          uint64_t edge_count, uint32_t *edges, uint32_t *deg, void *workspace,
                          uint64_t workspace_bytes, void *stream);
+
+/*
+ * Test hook (not needed to generate graphs): ba_generate_ws with the
+ * partition's region capacities scaled by cap_scale in (0, 1], so that most
+ * second endpoints take the overflow path (direct atomics) instead of the
+ * regions.  The result is the same for every scale; tests use it to check
+ * that path.  Errors: as ba_generate_ws, plus BA_EINVAL for a scale outside
+ * (0, 1] or deg NULL.
+ */
+int ba_test_generate_ws_scaled(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint32_t *deg,
+                               void *workspace, uint64_t workspace_bytes, double cap_scale, void *stream);
 
 /*
  * As ba_generate_range with 64-bit node IDs (any n with 2*n*d < 2^64).
@@ -139,10 +164,11 @@ int ba_degrees_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin,
                      uint64_t *xor_checksum, void *stream);
 
 /*
- * Which LDS counter tier the streaming degree kernel uses (process-wide,
- * host only; results are identical either way, only speed differs):
- *   BA_TIER_AUTO : the default; BA_TIER_64K when first_k > 16384 and the
- *                  targets expected in [16384, min(first_k, 65536)), about
+ * ba_degrees_range with an explicit choice of the LDS counter tier of the
+ * streaming kernel (results are identical on every tier; only speed differs):
+ *   BA_TIER_AUTO : what ba_degrees and ba_degrees_range use; BA_TIER_64K
+ *                  when first_k > 16384 and the targets expected in
+ *                  [16384, min(first_k, 65536)), about
  *                  (sqrt(min(first_k, 65536)) - 128) / sqrt(n) of them,
  *                  exceed 1.5% (all positions of the call below 2^32) or
  *                  1.8% (64-bit positions), i.e. for small n; else
@@ -153,11 +179,12 @@ int ba_degrees_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin,
  *   BA_TIER_64K  : 16-bit LDS counters for nodes below 65536 (128 KiB per
  *                  block, one block per compute unit), moved to the global
  *                  count 32768 at a time as they fill.
- * ba_degrees_tier sets the tier (BA_EINVAL for another value) and, when
- * previous is not NULL, stores the one it replaces.
+ * Errors: as ba_degrees_range, plus BA_EINVAL for another tier value.
  */
 enum { BA_TIER_AUTO = 0, BA_TIER_16K = 16, BA_TIER_64K = 64 };
-int ba_degrees_tier(int tier, int *previous);
+int ba_degrees_range_tier(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin,
+                          uint64_t edge_count, uint64_t first_k, uint64_t *deg,
+                          uint64_t *xor_checksum, int tier, void *stream);
 
 /*
  * Measurement hook for benchmarks (not needed to generate graphs).

@@ -39,7 +39,6 @@ __all__ = [
     "kernel_timing_read",
     "degrees",
     "degrees_range",
-    "degrees_tier",
     "Batch",
     "batch_plan_rounds",
     "batch_shape",
@@ -50,7 +49,7 @@ __all__ = [
     "library_path",
 ]
 
-BA_OK, BA_EINVAL, BA_ERANGE, BA_EDEVICE = 0, -1, -2, -4
+BA_OK, BA_EINVAL, BA_ERANGE, BA_ENOMEM, BA_EDEVICE = 0, -1, -2, -3, -4
 # kernel kinds of the timing hook (BA_KT_* in include/ba.h)
 KERNEL_KINDS = ("gen", "part", "hist", "stream", "other")
 
@@ -72,10 +71,11 @@ _SIGS = {
     "ba_generate_ws": (_int, [_u64, _u32, _u64, _p, _p, _p, _u64, _p]),
     "ba_generate_range_ws": (_int, [_u64, _u32, _u64, _u64, _u64, _p, _p, _p, _u64, _p]),
     "ba_generate_workspace_bytes": (_u64, [_u64, _u32, _u64]),
+    "ba_test_generate_ws_scaled": (_int, [_u64, _u32, _u64, _p, _p, _p, _u64, ctypes.c_double, _p]),
     "ba_generate_range_u64": (_int, [_u64, _u32, _u64, _u64, _u64, _p, _p]),
     "ba_degrees": (_int, [_u64, _u32, _u64, _u64, _p, _p, _p]),
     "ba_degrees_range": (_int, [_u64, _u32, _u64, _u64, _u64, _u64, _p, _p, _p]),
-    "ba_degrees_tier": (_int, [_int, _p]),
+    "ba_degrees_range_tier": (_int, [_u64, _u32, _u64, _u64, _u64, _u64, _p, _p, _int, _p]),
     "ba_strerror": (ctypes.c_char_p, [_int]),
     "ba_last_hip_error": (_int, []),
     "ba_host_divide": (_int, [_u32, _p, _p, _u64]),
@@ -273,14 +273,27 @@ def generate_range_u64(n: int, d: int, seed: int, begin: int, count: int, *, dev
     return out
 
 
-def degrees(n: int, d: int, seed: int, first_k: int, *, device=None) -> Tuple[torch.Tensor, int]:
+TIER_AUTO, TIER_16K, TIER_64K = 0, 16, 64
+
+
+def degrees(n: int, d: int, seed: int, first_k: int, *, tier: int = TIER_AUTO,
+            device=None) -> Tuple[torch.Tensor, int]:
     """Streaming degrees of nodes 0..first_k-1 (int64[first_k]) and the edge
-    XOR checksum (a Python int in 0..2^64-1); no edge is stored."""
+    XOR checksum (a Python int in 0..2^64-1); no edge is stored.  ``tier``
+    picks the streaming kernel's LDS counter tier (TIER_AUTO, TIER_16K or
+    TIER_64K; the result is the same on every tier)."""
     dev = _device(device)
-    deg = torch.empty(first_k, dtype=torch.int64, device=dev)
-    cs = torch.empty(1, dtype=torch.int64, device=dev)
     with torch.cuda.device(dev):
-        _check("ba_degrees", lib().ba_degrees(n, d, seed, first_k, _ptr(deg, dev), _ptr(cs, dev), _stream(dev)))
+        if tier == TIER_AUTO:
+            deg = torch.empty(first_k, dtype=torch.int64, device=dev)
+            cs = torch.empty(1, dtype=torch.int64, device=dev)
+            _check("ba_degrees", lib().ba_degrees(n, d, seed, first_k, _ptr(deg, dev), _ptr(cs, dev), _stream(dev)))
+        else:
+            deg = torch.zeros(first_k, dtype=torch.int64, device=dev)
+            cs = torch.zeros(1, dtype=torch.int64, device=dev)
+            _check("ba_degrees_range_tier",
+                   lib().ba_degrees_range_tier(n, d, seed, 0, n * d, first_k, _ptr(deg, dev), _ptr(cs, dev), tier,
+                                               _stream(dev)))
     return deg, int(cs.item()) & ((1 << 64) - 1)
 
 
@@ -293,6 +306,8 @@ def degrees_range(
     first_k: int,
     deg: torch.Tensor,
     cs: Optional[torch.Tensor] = None,
+    *,
+    tier: int = TIER_AUTO,
 ) -> None:
     """Accumulating form of :func:`degrees` over edges begin..begin+count-1:
     adds endpoint counts into ``deg`` (int64[first_k]) and XORs the edge words
@@ -304,21 +319,10 @@ def degrees_range(
         raise ValueError("cs must be int64 with one element")
     with torch.cuda.device(dev):
         _check(
-            "ba_degrees_range",
-            lib().ba_degrees_range(n, d, seed, begin, count, first_k, _ptr(deg, dev), _ptr(cs, dev), _stream(dev)),
+            "ba_degrees_range_tier",
+            lib().ba_degrees_range_tier(n, d, seed, begin, count, first_k, _ptr(deg, dev), _ptr(cs, dev), tier,
+                                        _stream(dev)),
         )
-
-
-TIER_AUTO, TIER_16K, TIER_64K = 0, 16, 64
-
-
-def degrees_tier(tier: int) -> int:
-    """Select the LDS counter tier of the streaming degree kernel
-    (TIER_AUTO, TIER_16K or TIER_64K; process-wide, results identical) and
-    return the previous setting."""
-    prev = ctypes.c_int(0)
-    _check("ba_degrees_tier", lib().ba_degrees_tier(tier, ctypes.byref(prev)))
-    return prev.value
 
 
 class BatchInfo(ctypes.Structure):

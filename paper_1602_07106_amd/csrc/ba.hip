@@ -62,7 +62,11 @@ struct GenArgs {
     uint32_t d;
     uint32_t *edges;  // 2*count uint32
     uint32_t *vlist;  // count uint32 second endpoints (degree pipeline), or null
+    uint32_t *deg;    // degree counts the second endpoints are added to (kDegAtomic)
 };
+
+// What the generator does with second endpoints besides storing the edges.
+enum DegMode { kDegNone = 0, kDegList = 1, kDegAtomic = 2 };
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
 {
@@ -288,8 +292,11 @@ __device__ __forceinline__ void chain_tile(uint32_t *stage, uint32_t tn, uint32_
 }
 
 // One chain step for every lane, then refill of the lanes that finished.
-// NARROW: all positions of the launch are below 2^32.
-template <bool NARROW, bool VEC16, bool VLIST>
+// NARROW: all positions of the launch are below 2^32.  DM: the second
+// endpoints also go to the degree pipeline's target list (kDegList), or are
+// added to deg by global atomics (kDegAtomic, the path that needs no
+// workspace: exact, but an order of magnitude slower).
+template <bool NARROW, bool VEC16, int DM>
 __global__ __launch_bounds__(kGenBlock) void k_gen_u32(GenArgs a)
 {
     __shared__ uint32_t stage_all[kGenWaves][kTile];
@@ -331,19 +338,27 @@ __global__ __launch_bounds__(kGenBlock) void k_gen_u32(GenArgs a)
                         *reinterpret_cast<uint4 *>(out + 2 * j) = make_uint4(u0, v0, u1, v1);
                     else
                         store_pair<false>(out, j, kTile, u0, v0, u1, v1);
-                    if constexpr (VLIST) *reinterpret_cast<uint2 *>(a.vlist + off + j) = make_uint2(v0, v1);
+                    if constexpr (DM == kDegList) *reinterpret_cast<uint2 *>(a.vlist + off + j) = make_uint2(v0, v1);
+                    if constexpr (DM == kDegAtomic) {
+                        deg_atomic_add(a.deg, v0, 1u);
+                        deg_atomic_add(a.deg, v1, 1u);
+                    }
                 }
             } else {
                 for (uint32_t j = 2 * lane; j < tn; j += 2 * kWave) {
                     uint32_t u0, u1, v0, v1;
                     flush_pair<NARROW, P>(a, stage, ibase, j, u0, u1, v0, v1);
                     store_pair<VEC16>(out, j, tn, u0, v0, u1, v1);
-                    if constexpr (VLIST) {
+                    if constexpr (DM == kDegList) {
                         // second endpoints alone, for the degree pipeline (8-byte aligned: j, off even)
                         if (j + 1 < tn)
                             *reinterpret_cast<uint2 *>(a.vlist + off + j) = make_uint2(v0, v1);
                         else
                             a.vlist[off + j] = v0;
+                    }
+                    if constexpr (DM == kDegAtomic) {
+                        deg_atomic_add(a.deg, v0, 1u);
+                        if (j + 1 < tn) deg_atomic_add(a.deg, v1, 1u);
                     }
                 }
             }
@@ -519,7 +534,7 @@ static int launch_timed(int kind, hipStream_t st, F &&launch)
     return rc;
 }
 
-template <bool N, bool V, bool L>
+template <bool N, bool V, int L>
 static int launch_gen_one(const GenArgs &a, hipStream_t st)
 {
     uint32_t grid = 0;
@@ -531,9 +546,10 @@ static int launch_gen_one(const GenArgs &a, hipStream_t st)
 }
 
 // Generator over edges begin .. begin+count-1 writing edge pairs to `edges`
-// and, when vlist is set (8-byte aligned), the second endpoints alone.
+// and, when vlist is set (8-byte aligned), the second endpoints alone, or,
+// when deg is set, adding the second endpoints to deg by atomics.
 static int launch_gen_u32(uint64_t begin, uint64_t count, uint32_t d, uint64_t seed, uint32_t *edges,
-                          hipStream_t st, uint32_t *vlist = nullptr)
+                          hipStream_t st, uint32_t *vlist = nullptr, uint32_t *deg = nullptr)
 {
     if (count == 0) return BA_OK;
     GenArgs a{};
@@ -545,29 +561,20 @@ static int launch_gen_u32(uint64_t begin, uint64_t count, uint32_t d, uint64_t s
     a.d = d;
     a.edges = edges;
     a.vlist = vlist;
+    a.deg = deg;
     const bool narrow = 2 * (begin + count) <= ((uint64_t)1 << 32);
     const bool vec16 = ((uintptr_t)edges & 15) == 0;
-    const int sel = (narrow ? 4 : 0) | (vec16 ? 2 : 0) | (vlist ? 1 : 0);
-    switch (sel) {
-    case 7: return launch_gen_one<true, true, true>(a, st);
-    case 6: return launch_gen_one<true, true, false>(a, st);
-    case 5: return launch_gen_one<true, false, true>(a, st);
-    case 4: return launch_gen_one<true, false, false>(a, st);
-    case 3: return launch_gen_one<false, true, true>(a, st);
-    case 2: return launch_gen_one<false, true, false>(a, st);
-    case 1: return launch_gen_one<false, false, true>(a, st);
-    default: return launch_gen_one<false, false, false>(a, st);
-    }
-}
-
-// Capacity scale of the partition regions (1 normally); BA_DEG_CAP_SCALE < 1
-// forces the overflow path, for tests.
-static double deg_cap_scale()
-{
-    const char *e = getenv("BA_DEG_CAP_SCALE");
-    if (!e) return 1.0;
-    const double x = atof(e);
-    return (x > 0.0 && x <= 1.0) ? x : 1.0;
+    const int dm = vlist ? kDegList : deg ? kDegAtomic : kDegNone;
+    auto pick = [&](auto n_t, auto v_t) {
+        constexpr bool N = decltype(n_t)::value, V = decltype(v_t)::value;
+        if (dm == kDegList) return launch_gen_one<N, V, kDegList>(a, st);
+        if (dm == kDegAtomic) return launch_gen_one<N, V, kDegAtomic>(a, st);
+        return launch_gen_one<N, V, kDegNone>(a, st);
+    };
+    using T = std::true_type;
+    using Fa = std::false_type;
+    if (narrow) return vec16 ? pick(T{}, T{}) : pick(T{}, Fa{});
+    return vec16 ? pick(Fa{}, T{}) : pick(Fa{}, Fa{});
 }
 
 // Largest pass (edges) of the degree pipeline whose layout for up to
@@ -588,7 +595,7 @@ static uint64_t deg_piece(uint64_t n, uint64_t count, uint64_t ws_bytes)
 // scan, histograms.  First endpoints are the caller's (a fill of d or the
 // closed-form range counts).
 static int degrees_of_targets(uint64_t n, uint32_t d, uint64_t begin, uint64_t count, uint32_t *deg, void *ws,
-                              bool fresh, hipStream_t st)
+                              bool fresh, double cap_scale, hipStream_t st)
 {
     uint32_t P = 0;
     int rc = persistent_grid(k_deg_part, kPBlock, &P);
@@ -600,7 +607,7 @@ static int degrees_of_targets(uint64_t n, uint32_t d, uint64_t begin, uint64_t c
     a.d = d;
     a.deg = deg;
     a.ws = (unsigned char *)ws;
-    a.scale = deg_cap_scale();
+    a.scale = cap_scale;
     a.fresh = fresh ? 1u : 0u;
     if ((rc = launch_timed(BA_KT_OTHER, st, [&] { hipLaunchKernelGGL(k_deg_plan, dim3(1), dim3(1024), 0, st, a); })))
         return rc;
@@ -633,7 +640,8 @@ static int degrees_of_targets(uint64_t n, uint32_t d, uint64_t begin, uint64_t c
 // graph's first endpoints, just filled), so the first pass may store counts
 // without reading deg.
 static int gen_with_degrees(uint64_t n, uint32_t d, uint64_t seed, uint64_t begin, uint64_t count,
-                            uint32_t *edges, uint32_t *deg, void *ws, uint64_t ws_bytes, bool fresh, hipStream_t st)
+                            uint32_t *edges, uint32_t *deg, void *ws, uint64_t ws_bytes, bool fresh, hipStream_t st,
+                            double cap_scale = 1.0)
 {
     if (count == 0) return BA_OK;
     const uint64_t piece = deg_piece(n, count, ws_bytes);
@@ -644,25 +652,10 @@ static int gen_with_degrees(uint64_t n, uint32_t d, uint64_t seed, uint64_t begi
         int rc = launch_gen_u32(begin + done, C, d, seed, edges + 2 * done, st,
                                 (uint32_t *)((unsigned char *)ws + p.o_V));
         if (rc) return rc;
-        rc = degrees_of_targets(n, d, begin + done, C, deg, ws, fresh && done == 0, st);
+        rc = degrees_of_targets(n, d, begin + done, C, deg, ws, fresh && done == 0, cap_scale, st);
         if (rc) return rc;
     }
     return BA_OK;
-}
-
-// Workspace from the stream-ordered allocator for calls that bring none.
-static int gen_with_degrees_alloc(uint64_t n, uint32_t d, uint64_t seed, uint64_t begin, uint64_t count,
-                                  uint32_t *edges, uint32_t *deg, bool fresh, hipStream_t st)
-{
-    if (count == 0) return BA_OK;
-    const uint64_t piece = count < kPieceMax ? count : kPieceMax;
-    const uint64_t bytes = make_deg_plan(n, piece, kPBlocksMax).bytes;
-    void *ws = nullptr;
-    int rc = hip_check(hipMallocAsync(&ws, bytes, st));
-    if (rc) return rc;
-    rc = gen_with_degrees(n, d, seed, begin, count, edges, deg, ws, bytes, fresh, st);
-    const int rc2 = hip_check(hipFreeAsync(ws, st));
-    return rc ? rc : rc2;
 }
 
 template <class T>
@@ -715,11 +708,15 @@ struct BatchShape {
 constexpr BatchShape kBatchShapes[] = {{0, 4}, {1, 4}, {2, 4}, {0, 8}, {1, 8}};
 constexpr int kBatchShapeCount = sizeof(kBatchShapes) / sizeof(kBatchShapes[0]);
 constexpr int kMaxDevices = 64;
-// Chosen shape per device: written only by ba_batch_autotune, -1 = default (shape 0).
-static int g_batch_shape[kMaxDevices] = {
-    -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
-    -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
-    -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+// Tuned shape per device, -1 = default (shape 0): the library's one piece of
+// process-wide state, a cache that ba_batch_autotune writes and the launches
+// read (atomics, so calls from several host threads do not race).
+static std::atomic<int> g_batch_shape[kMaxDevices];
+static int batch_shape_of(int slot)
+{
+    const int s = g_batch_shape[slot].load(std::memory_order_relaxed);
+    return s <= 0 || s >= kBatchShapeCount ? 0 : s;
+}
 
 template <uint32_t TILE, uint32_t WAVES>
 static int launch_batch_shape(BatchArgs a, hipStream_t st)
@@ -798,6 +795,9 @@ static int check_generate(uint64_t n, uint32_t d, uint64_t begin, uint64_t count
 {
     uint64_t m;
     if (!graph_fits(n, d, &m) || n > ((uint64_t)1 << 32)) return BA_ERANGE;
+    // uint32 degrees: node v holds its d first endpoints and at most the
+    // second endpoints of edges d*v .. m-1, so every count is at most m + d
+    if (deg && m + d > (uint64_t)UINT32_MAX) return BA_ERANGE;
     if (begin > m || count > m - begin) return BA_EINVAL;
     if ((count && !edges) || ((uintptr_t)edges & 3) || ((uintptr_t)deg & 3)) return BA_EINVAL;
     return BA_OK;
@@ -820,8 +820,8 @@ int ba_generate(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint32_t
     if (m && !edges) return BA_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     if ((rc = fill_first_endpoints_whole(n, d, deg, st))) return rc;
-    if (deg) return gen_with_degrees_alloc(n, d, seed, 0, m, edges, deg, true, st);
-    return launch_gen_u32(0, m, d, seed, edges, st);
+    // no workspace: second endpoints by global atomics (no allocation)
+    return launch_gen_u32(0, m, d, seed, edges, st, nullptr, deg);
 }
 
 int ba_generate_ws(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint32_t *deg, void *workspace,
@@ -832,8 +832,8 @@ int ba_generate_ws(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint3
     if (rc) return rc;
     graph_fits(n, d, &m);
     if (m && !edges) return BA_EINVAL;
-    if (deg && m && (deg_piece(n, m, workspace_bytes) == 0 || !workspace || ((uintptr_t)workspace & 255)))
-        return BA_EINVAL;
+    if (deg && m && (!workspace || ((uintptr_t)workspace & 255))) return BA_EINVAL;
+    if (deg && m && deg_piece(n, m, workspace_bytes) == 0) return BA_ENOMEM;
     hipStream_t st = (hipStream_t)stream;
     if ((rc = fill_first_endpoints_whole(n, d, deg, st))) return rc;
     if (deg) return gen_with_degrees(n, d, seed, 0, m, edges, deg, workspace, workspace_bytes, true, st);
@@ -848,7 +848,7 @@ int ba_generate_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin
     hipStream_t st = (hipStream_t)stream;
     if (deg) {
         if ((rc = launch_first_endpoints<uint32_t>(deg, n, edge_begin, edge_count, d, n, st))) return rc;
-        return gen_with_degrees_alloc(n, d, seed, edge_begin, edge_count, edges, deg, false, st);
+        return launch_gen_u32(edge_begin, edge_count, d, seed, edges, st, nullptr, deg);
     }
     return launch_gen_u32(edge_begin, edge_count, d, seed, edges, st);
 }
@@ -859,9 +859,8 @@ int ba_generate_range_ws(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_be
 {
     int rc = check_generate(n, d, edge_begin, edge_count, edges, deg);
     if (rc) return rc;
-    if (deg && edge_count &&
-        (deg_piece(n, edge_count, workspace_bytes) == 0 || !workspace || ((uintptr_t)workspace & 255)))
-        return BA_EINVAL;
+    if (deg && edge_count && (!workspace || ((uintptr_t)workspace & 255))) return BA_EINVAL;
+    if (deg && edge_count && deg_piece(n, edge_count, workspace_bytes) == 0) return BA_ENOMEM;
     hipStream_t st = (hipStream_t)stream;
     if (deg) {
         if ((rc = launch_first_endpoints<uint32_t>(deg, n, edge_begin, edge_count, d, n, st))) return rc;
@@ -869,6 +868,21 @@ int ba_generate_range_ws(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_be
                                 st);
     }
     return launch_gen_u32(edge_begin, edge_count, d, seed, edges, st);
+}
+
+int ba_test_generate_ws_scaled(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint32_t *deg,
+                               void *workspace, uint64_t workspace_bytes, double cap_scale, void *stream)
+{
+    if (!(cap_scale > 0.0 && cap_scale <= 1.0) || !deg) return BA_EINVAL;
+    uint64_t m = 0;
+    int rc = check_generate(n, d, 0, 0, edges, deg);
+    if (rc) return rc;
+    graph_fits(n, d, &m);
+    if (m && (!edges || !workspace || ((uintptr_t)workspace & 255))) return BA_EINVAL;
+    if (m && deg_piece(n, m, workspace_bytes) == 0) return BA_ENOMEM;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = fill_first_endpoints_whole(n, d, deg, st))) return rc;
+    return gen_with_degrees(n, d, seed, 0, m, edges, deg, workspace, workspace_bytes, true, st, cap_scale);
 }
 
 uint64_t ba_generate_workspace_bytes(uint64_t n, uint32_t d, uint64_t edge_count)
@@ -902,10 +916,11 @@ int ba_generate_range_u64(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_b
     return hip_check(hipGetLastError());
 }
 
-int ba_degrees_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin, uint64_t edge_count,
-                     uint64_t first_k, uint64_t *deg, uint64_t *xor_checksum, void *stream)
+int ba_degrees_range_tier(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin, uint64_t edge_count,
+                          uint64_t first_k, uint64_t *deg, uint64_t *xor_checksum, int tier, void *stream)
 {
     uint64_t m;
+    if (tier != BA_TIER_AUTO && tier != BA_TIER_16K && tier != BA_TIER_64K) return BA_EINVAL;
     if (!graph_fits(n, d, &m)) return BA_ERANGE;
     if (first_k > n || edge_begin > m || edge_count > m - edge_begin) return BA_EINVAL;
     if ((first_k && !deg) || ((uintptr_t)deg & 7) || ((uintptr_t)xor_checksum & 7)) return BA_EINVAL;
@@ -914,15 +929,14 @@ int ba_degrees_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin,
         int rc = launch_first_endpoints<uint64_t>(deg, n, edge_begin, edge_count, d, first_k, st);
         if (rc) return rc;
     }
-    return launch_stream(n, edge_begin, edge_count, d, seed, first_k, deg, xor_checksum, st);
+    return launch_stream(n, edge_begin, edge_count, d, seed, first_k, deg, xor_checksum, tier, st);
 }
 
-int ba_degrees_tier(int tier, int *previous)
+int ba_degrees_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin, uint64_t edge_count,
+                     uint64_t first_k, uint64_t *deg, uint64_t *xor_checksum, void *stream)
 {
-    if (tier != BA_TIER_AUTO && tier != BA_TIER_16K && tier != BA_TIER_64K) return BA_EINVAL;
-    const int old = g_stream_tier.exchange(tier, std::memory_order_relaxed);
-    if (previous) *previous = old;
-    return BA_OK;
+    return ba_degrees_range_tier(n, d, seed, edge_begin, edge_count, first_k, deg, xor_checksum, BA_TIER_AUTO,
+                                 stream);
 }
 
 int ba_degrees(uint64_t n, uint32_t d, uint64_t seed, uint64_t first_k, uint64_t *deg,
@@ -1002,8 +1016,7 @@ int ba_batch_launch(const ba_batch_info *info, const void *workspace, uint32_t *
     int slot = 0;
     int rc = current_device_slot(&slot);
     if (rc) return rc;
-    const int shape = g_batch_shape[slot] < 0 ? 0 : g_batch_shape[slot];
-    return launch_batch(shape, info, workspace, edges, (hipStream_t)stream);
+    return launch_batch(batch_shape_of(slot), info, workspace, edges, (hipStream_t)stream);
 }
 
 int ba_batch_autotune(const ba_batch_info *info, const void *workspace, uint32_t *edges, uint64_t edges_len,
@@ -1043,7 +1056,7 @@ int ba_batch_autotune(const ba_batch_info *info, const void *workspace, uint32_t
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    g_batch_shape[slot] = best;
+    g_batch_shape[slot].store(best, std::memory_order_relaxed);
     if (shape_out) *shape_out = best;
     return BA_OK;
 }
@@ -1063,7 +1076,7 @@ int ba_batch_current_shape(int *shape)
     int slot = 0;
     int rc = current_device_slot(&slot);
     if (rc) return rc;
-    *shape = g_batch_shape[slot] < 0 ? 0 : g_batch_shape[slot];
+    *shape = batch_shape_of(slot);
     return BA_OK;
 }
 
@@ -1256,7 +1269,10 @@ const char *ba_strerror(int status)
     switch (status) {
     case BA_OK: return "success";
     case BA_EINVAL: return "invalid argument (null or misaligned buffer, range past n*d, or first_k > n)";
-    case BA_ERANGE: return "graph too large (2*n*d must fit 64 bits; uint32 output needs n <= 2^32)";
+    case BA_ERANGE:
+        return "graph too large (2*n*d must fit 64 bits; uint32 output needs n <= 2^32; uint32 degrees need "
+               "n*d + d < 2^32)";
+    case BA_ENOMEM: return "workspace or static scratch too small for the smallest pass";
     case BA_EDEVICE: return "HIP call failed (see ba_last_hip_error)";
     default: return "unknown status";
     }

@@ -341,9 +341,6 @@ static int launch_stream_packed(const StreamArgs &a0, hipStream_t st)
     });
 }
 
-// LDS counter tier of the streaming launches (BA_TIER_*).
-static std::atomic<int> g_stream_tier{BA_TIER_AUTO};
-
 // BA_TIER_AUTO.  A target lands on node v with probability close to
 // 1 / (2 sqrt(v n)), so about (sqrt(min(k, 65536)) - 128) / sqrt(n) of all
 // targets fall in [16384, min(k, 65536)): the global atomics the 64K tier
@@ -354,17 +351,16 @@ static std::atomic<int> g_stream_tier{BA_TIER_AUTO};
 // (first_k = 10^5, 32-bit positions) the tiers break even near n = 7e7, a
 // share of ~1.5%.  With 64-bit positions the 64K tier costs more compute
 // (~35% at n = 2^30) but the served mix still favours it above ~1.8%.
-static int stream_tier(uint64_t n, uint64_t k, bool narrow)
+static int stream_tier(uint64_t n, uint64_t k, bool narrow, int tier)
 {
-    const int t = g_stream_tier.load(std::memory_order_relaxed);
-    if (t != BA_TIER_AUTO) return t;
+    if (tier != BA_TIER_AUTO) return tier;
     if (k <= kLdsNodes) return BA_TIER_16K;
     const double share = (std::sqrt((double)std::min<uint64_t>(k, kPackedNodes)) - 128.0) / std::sqrt((double)n);
     return share > (narrow ? 0.015 : 0.018) ? BA_TIER_64K : BA_TIER_16K;
 }
 
 static int launch_stream(uint64_t n, uint64_t begin, uint64_t count, uint32_t d, uint64_t seed, uint64_t k,
-                         uint64_t *deg, uint64_t *cs, hipStream_t st)
+                         uint64_t *deg, uint64_t *cs, int tier, hipStream_t st)
 {
     if (count == 0) return BA_OK;
     StreamArgs a{};
@@ -378,7 +374,7 @@ static int launch_stream(uint64_t n, uint64_t begin, uint64_t count, uint32_t d,
     a.cs = cs;
     const bool narrow = 2 * (begin + count) <= ((uint64_t)1 << 32);
     const bool pow2 = a.div.pow2 != 0;
-    if (stream_tier(n, k, narrow) == BA_TIER_64K) {
+    if (stream_tier(n, k, narrow, tier) == BA_TIER_64K) {
         if (narrow) return pow2 ? launch_stream_packed<true, true>(a, st) : launch_stream_packed<true, false>(a, st);
         return pow2 ? launch_stream_packed<false, true>(a, st) : launch_stream_packed<false, false>(a, st);
     }

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_function():
 
 def test_strerror_covers_every_status():
     L = ba.lib()
-    for st in [ba.BA_OK, ba.BA_EINVAL, ba.BA_ERANGE, ba.BA_EDEVICE, 12345]:
+    for st in [ba.BA_OK, ba.BA_EINVAL, ba.BA_ERANGE, ba.BA_ENOMEM, ba.BA_EDEVICE, 12345]:
         assert L.ba_strerror(st)
     assert L.ba_strerror(12345) == b"unknown status"
 
@@ -233,15 +233,31 @@ def test_model_argument_checks_without_gpu():
     assert L.ba_generate_model(100, 2, 1, 10, 0, None, 0, 5, 0, None, None) == ba.BA_OK  # empty range
 
 
-def test_degrees_tier_setting():
-    import paper_1602_07106_amd as ba
-    prev = ba.degrees_tier(ba.TIER_64K)
-    try:
-        assert ba.degrees_tier(ba.TIER_16K) == ba.TIER_64K
-        assert ba.degrees_tier(ba.TIER_AUTO) == ba.TIER_16K
-        for bad in (1, 32, -1, 65):
-            with pytest.raises(ba.BAError):
-                ba.degrees_tier(bad)
-        assert ba.degrees_tier(ba.TIER_AUTO) == ba.TIER_AUTO
-    finally:
-        ba.degrees_tier(prev)
+def test_streaming_tier_is_checked_per_call():
+    L = ba.lib()
+    for bad in (1, 32, -1, 65):
+        assert L.ba_degrees_range_tier(10, 2, 0, 0, 20, 5, FAKE, None, bad, None) == ba.BA_EINVAL
+    # valid tiers on empty work: nothing to launch
+    for t in (ba.TIER_AUTO, ba.TIER_16K, ba.TIER_64K):
+        assert L.ba_degrees_range_tier(10, 2, 0, 0, 0, 0, None, None, t, None) == ba.BA_OK
+
+
+def test_uint32_degrees_that_could_wrap_are_refused():
+    # node v holds d first endpoints plus at most m - d*v second endpoints:
+    # counts stay below 2^32 only while n*d + d < 2^32
+    L = ba.lib()
+    assert L.ba_generate(1, 1 << 31, 0, FAKE, FAKE, None) == ba.BA_ERANGE
+    assert L.ba_generate(3, (1 << 31) - 1, 0, FAKE, FAKE, None) == ba.BA_ERANGE
+    assert L.ba_generate_range(3, (1 << 31) - 1, 0, 0, 1, FAKE, FAKE, None) == ba.BA_ERANGE
+    assert L.ba_generate_ws(1 << 20, 1 << 12, 0, FAKE, FAKE, FAKE, 1 << 40, None) == ba.BA_ERANGE
+
+
+def test_workspace_too_small_is_enomem_and_bad_pointers_einval():
+    L = ba.lib()
+    n, d = 1 << 20, 4
+    need = ba.workspace_bytes(n, d, n * d)
+    assert need > 0
+    assert L.ba_generate_ws(n, d, 0, FAKE, FAKE, FAKE, 1000, None) == ba.BA_ENOMEM
+    assert L.ba_generate_range_ws(n, d, 0, 5, 1 << 20, FAKE, FAKE, FAKE, 1000, None) == ba.BA_ENOMEM
+    assert L.ba_generate_ws(n, d, 0, FAKE, FAKE, None, need, None) == ba.BA_EINVAL
+    assert L.ba_generate_ws(n, d, 0, FAKE, FAKE, FAKE + 4, need, None) == ba.BA_EINVAL

@@ -1,6 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle,
 element by element and bit-exact (the method is integer-only, so the
 tolerance is zero)."""
+import ctypes
 import random
 import sys
 
@@ -145,22 +146,14 @@ def test_streaming_ranges_accumulate_including_wide_positions():
     assert (int(cs.item()) & M64) == rcs
 
 
-@pytest.fixture
-def _tier():
-    prev = ba.degrees_tier(ba.TIER_AUTO)
-    yield
-    ba.degrees_tier(prev)
-
-
 @pytest.mark.parametrize("tier", [ba.TIER_16K, ba.TIER_64K])
 @pytest.mark.parametrize("n,d,seed,k", [(100000, 4, 1, 100000), (20000, 5, 3, 1000), (70001, 9, 77, 65537),
                                         (3000, 2, 5, 3000)])
-def test_streaming_degrees_on_either_lds_tier(_tier, tier, n, d, seed, k):
+def test_streaming_degrees_on_either_lds_tier(tier, n, d, seed, k):
     """Both LDS counter tiers give the oracle's counts, whichever holds the
     node (LDS word or global atomic) and at the 65536-node tier edge."""
     _say("degrees tier", tier, n, d, seed, k)
-    ba.degrees_tier(tier)
-    deg, cs = ba.degrees(n, d, seed, k)
+    deg, cs = ba.degrees(n, d, seed, k, tier=tier)
     torch.cuda.synchronize()
     E, _ = oracle.bb_generate(n, d, seed)
     assert np.array_equal(_u64(deg), oracle.count_degrees(E, n)[:k])
@@ -169,7 +162,7 @@ def test_streaming_degrees_on_either_lds_tier(_tier, tier, n, d, seed, k):
 
 @pytest.mark.parametrize("tier", [ba.TIER_16K, ba.TIER_64K])
 @pytest.mark.parametrize("begin,d", [(0, 1 << 24), ((1 << 31) - (1 << 12), 1 << 31)])
-def test_streaming_degrees_of_two_very_heavy_nodes(_tier, tier, begin, d):
+def test_streaming_degrees_of_two_very_heavy_nodes(tier, begin, d):
     """n = 2 with a huge d: about 2^25 targets land on nodes 0 and 1, so every
     block of the 64K tier takes the 16-bit counters of both halves of one LDS
     word past 0x7FFF several times (up to the 32768-per-round maximum).  The
@@ -177,10 +170,9 @@ def test_streaming_degrees_of_two_very_heavy_nodes(_tier, tier, begin, d):
     boundary between nodes 0 and 1)."""
     n, count, k = 2, 1 << 25, 2
     _say("heavy degrees", tier, begin, d)
-    ba.degrees_tier(tier)
     deg = torch.zeros(k, dtype=torch.int64, device="cuda")
     cs = torch.zeros(1, dtype=torch.int64, device="cuda")
-    ba.degrees_range(n, d, seed := 11, begin, count, k, deg, cs)
+    ba.degrees_range(n, d, seed := 11, begin, count, k, deg, cs, tier=tier)
     torch.cuda.synchronize()
     ref, rcs, _ = oracle.stream(d, seed, begin, count, k)
     got = _u64(deg)
@@ -191,20 +183,19 @@ def test_streaming_degrees_of_two_very_heavy_nodes(_tier, tier, begin, d):
 
 @pytest.mark.parametrize("d", [16, 12])
 @pytest.mark.parametrize("tier", [ba.TIER_16K, ba.TIER_64K])
-def test_streaming_tiers_on_wide_positions_accumulate(_tier, tier, d):
+def test_streaming_tiers_on_wide_positions_accumulate(tier, d):
     """Both tiers on ranges with 64-bit positions (around 2^31 and 2^32 and
     beyond), first_k = 10^5, so LDS counters, the 16-bit wrap moves and the
     global atomics all run on the wide kernels, with d a power of two (shift)
     and not (multiply-high division)."""
     n, seed, k = 1 << 30, 9, 100000
-    ba.degrees_tier(tier)
     deg = torch.zeros(k, dtype=torch.int64, device="cuda")
     cs = torch.zeros(1, dtype=torch.int64, device="cuda")
     ref = np.zeros(k, dtype=np.uint64)
     rcs = 0
     for b, c in [((1 << 31) - 70000, 140000), ((1 << 32) - 100000, 300000), (n * d - 250000, 250000)]:
         _say("tier range", tier, d, b, c)
-        ba.degrees_range(n, d, seed, b, c, k, deg, cs)
+        ba.degrees_range(n, d, seed, b, c, k, deg, cs, tier=tier)
         ref, rcs, _ = oracle.stream(d, seed, b, c, k, ref, rcs)
     torch.cuda.synchronize()
     assert np.array_equal(_u64(deg), ref)
@@ -212,40 +203,77 @@ def test_streaming_tiers_on_wide_positions_accumulate(_tier, tier, d):
 
 
 @pytest.mark.parametrize("tier", [ba.TIER_AUTO, ba.TIER_16K, ba.TIER_64K])
-def test_streaming_checksum_alone(_tier, tier):
+def test_streaming_checksum_alone(tier):
     """first_k = 0: no degree is counted, the checksum is still every edge's."""
     n, d, seed = 50000, 7, 13
     _say("checksum only", tier)
-    ba.degrees_tier(tier)
-    deg, cs = ba.degrees(n, d, seed, 0)
+    deg, cs = ba.degrees(n, d, seed, 0, tier=tier)
     torch.cuda.synchronize()
     assert deg.numel() == 0
     E, _ = oracle.bb_generate(n, d, seed)
     assert cs == oracle.checksum_E(E)
 
 
-def test_degrees_through_the_stream_ordered_allocator():
-    # ba_generate without a workspace takes one from hipMallocAsync
+def _pool_used_high():
+    """High-water mark of the device's stream-ordered pool (bytes)."""
+    import ctypes
+
+    hip = ctypes.CDLL("libamdhip64.so")
+    pool = ctypes.c_void_p()
+    assert hip.hipDeviceGetDefaultMemPool(ctypes.byref(pool), torch.cuda.current_device()) == 0
+    v = ctypes.c_uint64(0)
+    assert hip.hipMemPoolGetAttribute(pool, 8, ctypes.byref(v)) == 0  # hipMemPoolAttrUsedMemHigh
+    return pool, v.value, hip
+
+
+def test_degrees_without_a_workspace_allocate_nothing():
+    # ba_generate / ba_generate_range with deg and no workspace: global
+    # atomics from the generator, no device allocation of any kind
     n, d, seed = 70000, 6, 21
+    m = n * d
     _say("generate deg no-ws", n, d, seed)
     E, _ = oracle.bb_generate(n, d, seed)
-    out = torch.empty(2 * n * d, dtype=torch.int32, device="cuda")
+    out = torch.empty(2 * m, dtype=torch.int32, device="cuda")
     deg = torch.empty(n, dtype=torch.int32, device="cuda")
+    racc = torch.zeros(n, dtype=torch.int32, device="cuda")
+    rout = torch.empty(2 * m, dtype=torch.int32, device="cuda")
     st = torch.cuda.current_stream().cuda_stream
-    assert ba.lib().ba_generate(n, d, seed, out.data_ptr(), deg.data_ptr(), st) == 0
-    torch.cuda.synchronize()
+
+    def run():
+        racc.zero_()
+        assert ba.lib().ba_generate(n, d, seed, out.data_ptr(), deg.data_ptr(), st) == 0
+        for b, c in [(0, 1000), (1000, 12345), (13345, m - 13345)]:
+            assert ba.lib().ba_generate_range(n, d, seed, b, c, rout.data_ptr() + 8 * b, racc.data_ptr(), st) == 0
+        torch.cuda.synchronize()
+
+    run()  # first launches load the kernels
+    pool, _, hip = _pool_used_high()
+    zero = ctypes.c_uint64(0)
+    assert hip.hipMemPoolSetAttribute(pool, 8, ctypes.byref(zero)) == 0  # reset the high-water mark
+    free0 = torch.cuda.mem_get_info()[0]
+    run()
+    assert _pool_used_high()[1] == 0
+    assert torch.cuda.mem_get_info()[0] == free0
     assert np.array_equal(_u32(out), E)
-    assert np.array_equal(_u32(deg).astype(np.uint64), oracle.count_degrees(E, n))
+    assert np.array_equal(_u32(rout), E)
+    ref = oracle.count_degrees(E, n)
+    assert np.array_equal(_u32(deg).astype(np.uint64), ref)
+    assert np.array_equal(_u32(racc).astype(np.uint64), ref)
 
 
-@pytest.mark.parametrize("scale", ["0.02", "0.5"])
-def test_degree_overflow_fallback_is_exact(scale, monkeypatch):
-    # shrunken L1 capacities push most second endpoints through the fallback
+@pytest.mark.parametrize("scale", [0.02, 0.5])
+def test_degree_overflow_fallback_is_exact(scale):
+    # shrunken region capacities push most second endpoints through the fallback
     n, d, seed = 300000, 5, 8
+    m = n * d
     _say("overflow", scale)
-    monkeypatch.setenv("BA_DEG_CAP_SCALE", scale)
     E, _ = oracle.bb_generate(n, d, seed)
-    edges, deg = ba.generate(n, d, seed, degrees=True)
+    edges = torch.empty(2 * m, dtype=torch.int32, device="cuda")
+    deg = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = ba.workspace(n, d, m)
+    st = torch.cuda.current_stream().cuda_stream
+    assert ba.lib().ba_test_generate_ws_scaled(n, d, seed, edges.data_ptr(), deg.data_ptr(), ws.data_ptr(),
+                                               ws.numel(), scale, st) == 0
     torch.cuda.synchronize()
     assert np.array_equal(_u32(edges), E)
     assert np.array_equal(_u32(deg).astype(np.uint64), oracle.count_degrees(E, n))
