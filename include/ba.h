@@ -122,6 +122,32 @@ int ba_generate_range_ws(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_be
                          uint64_t workspace_bytes, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ba_generate_ws with the degree pipeline's workspace taken from a fixed
+ * static device array of BA_STATIC_SCRATCH_BYTES (256 MiB) instead of the
+ * caller.  Nothing is allocated or freed by the call.  Each GPU the library
+ * runs on holds its own copy of that array from the moment the library's
+ * code is loaded on it until the process ends; the first call on a device
+ * looks up the copy's address (a HIP call that allocates nothing).
+ *   edges, deg : as ba_generate_ws (deg may be NULL: then no scratch is used).
+ * The graph is processed in passes of as many edges as the scratch holds
+ * (about 2.26e7 edges a pass at n = 2^26, so the n = 2^26, d = 16 graph
+ * takes 48 passes; slower than ba_generate_ws with a whole workspace, same
+ * result).  Every call on one GPU shares that GPU's scratch and the scratch
+ * keeps whatever the last call left there (each pass initialises what it
+ * reads): calls with deg that overlap on one GPU (on different streams,
+ * or from different host threads without ordering) race and give wrong
+ * degrees; order them on one stream.
+ * Errors: as ba_generate_ws, with BA_ENOMEM (checked on the host, before
+ * any device call) when deg is given and not even a pass of 2^20 edges fits
+ * the scratch, i.e. for n above about 2.29e8.
+ */
+#define BA_STATIC_SCRATCH_BYTES ((uint64_t)256 << 20)
+int ba_generate_static(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint32_t *deg,
+                       void *stream);
+
+/*
  * Test hook (not needed to generate graphs): ba_generate_ws with the
  * partition's region capacities scaled by cap_scale in (0, 1], so that most
  * second endpoints take the overflow path (direct atomics) instead of the

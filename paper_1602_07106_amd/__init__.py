@@ -71,6 +71,7 @@ _SIGS = {
     "ba_generate_ws": (_int, [_u64, _u32, _u64, _p, _p, _p, _u64, _p]),
     "ba_generate_range_ws": (_int, [_u64, _u32, _u64, _u64, _u64, _p, _p, _p, _u64, _p]),
     "ba_generate_workspace_bytes": (_u64, [_u64, _u32, _u64]),
+    "ba_generate_static": (_int, [_u64, _u32, _u64, _p, _p, _p]),
     "ba_test_generate_ws_scaled": (_int, [_u64, _u32, _u64, _p, _p, _p, _u64, ctypes.c_double, _p]),
     "ba_generate_range_u64": (_int, [_u64, _u32, _u64, _u64, _u64, _p, _p]),
     "ba_degrees": (_int, [_u64, _u32, _u64, _u64, _p, _p, _p]),

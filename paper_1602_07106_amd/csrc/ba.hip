@@ -37,6 +37,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <utility>
@@ -578,16 +579,19 @@ static int launch_gen_u32(uint64_t begin, uint64_t count, uint32_t d, uint64_t s
 }
 
 // Largest pass (edges) of the degree pipeline whose layout for up to
-// kPBlocksMax partition blocks fits ws_bytes; 0 if none.
-static uint64_t deg_piece(uint64_t n, uint64_t count, uint64_t ws_bytes)
+// pmax partition blocks fits ws_bytes (a multiple of the partition chunk
+// when several passes are needed); 0 if not even the smallest pass fits.
+static uint64_t deg_piece(uint64_t n, uint64_t count, uint64_t ws_bytes, uint32_t pmax)
 {
-    uint64_t piece = count < kPieceMax ? count : kPieceMax;
-    while (piece > 0 && make_deg_plan(n, piece, kPBlocksMax).bytes > ws_bytes) {
-        if (piece <= kPieceMin) return 0;
-        piece /= 2;
-        if (piece < kPieceMin) piece = kPieceMin;
+    uint64_t hi = count < kPieceMax ? count : kPieceMax;
+    if (make_deg_plan(n, hi, pmax).bytes <= ws_bytes) return hi;
+    uint64_t lo = hi < kPieceMin ? hi : kPieceMin;
+    if (lo == hi || make_deg_plan(n, lo, pmax).bytes > ws_bytes) return 0;
+    while (hi - lo > 1) {  // the layout grows with the pass
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (make_deg_plan(n, mid, pmax).bytes <= ws_bytes) lo = mid; else hi = mid;
     }
-    return piece;
+    return lo / kPChunk * kPChunk;
 }
 
 // Second endpoints of edges begin .. begin+count-1 (the target list the
@@ -595,12 +599,12 @@ static uint64_t deg_piece(uint64_t n, uint64_t count, uint64_t ws_bytes)
 // scan, histograms.  First endpoints are the caller's (a fill of d or the
 // closed-form range counts).
 static int degrees_of_targets(uint64_t n, uint32_t d, uint64_t begin, uint64_t count, uint32_t *deg, void *ws,
-                              bool fresh, double cap_scale, hipStream_t st)
+                              bool fresh, double cap_scale, uint32_t pmax, hipStream_t st)
 {
     uint32_t P = 0;
     int rc = persistent_grid(k_deg_part, kPBlock, &P);
     if (rc) return rc;
-    if (P > kPBlocksMax) P = kPBlocksMax;
+    if (P > pmax) P = pmax;
     DegArgs a{};
     a.p = make_deg_plan(n, count, P);
     a.B = begin;
@@ -636,23 +640,23 @@ static int degrees_of_targets(uint64_t n, uint32_t d, uint64_t begin, uint64_t c
 }
 
 // Edges [begin, begin+count) written to `edges`, their second endpoints
-// added to deg, pass by pass.  fresh: deg[v] = d for every node (a whole
-// graph's first endpoints, just filled), so the first pass may store counts
-// without reading deg.
+// added to deg, pass by pass, with at most pmax partition blocks.  fresh:
+// deg[v] = d for every node (a whole graph's first endpoints, just filled),
+// so the first pass may store counts without reading deg.
 static int gen_with_degrees(uint64_t n, uint32_t d, uint64_t seed, uint64_t begin, uint64_t count,
                             uint32_t *edges, uint32_t *deg, void *ws, uint64_t ws_bytes, bool fresh, hipStream_t st,
-                            double cap_scale = 1.0)
+                            double cap_scale = 1.0, uint32_t pmax = kPBlocksMax)
 {
     if (count == 0) return BA_OK;
-    const uint64_t piece = deg_piece(n, count, ws_bytes);
+    const uint64_t piece = deg_piece(n, count, ws_bytes, pmax);
     if (piece == 0 || !ws || ((uintptr_t)ws & 255)) return BA_EINVAL;
     for (uint64_t done = 0; done < count; done += piece) {
         const uint64_t C = count - done < piece ? count - done : piece;
-        const DegPlan p = make_deg_plan(n, C, kPBlocksMax);
+        const DegPlan p = make_deg_plan(n, C, pmax);
         int rc = launch_gen_u32(begin + done, C, d, seed, edges + 2 * done, st,
                                 (uint32_t *)((unsigned char *)ws + p.o_V));
         if (rc) return rc;
-        rc = degrees_of_targets(n, d, begin + done, C, deg, ws, fresh && done == 0, cap_scale, st);
+        rc = degrees_of_targets(n, d, begin + done, C, deg, ws, fresh && done == 0, cap_scale, pmax, st);
         if (rc) return rc;
     }
     return BA_OK;
@@ -786,6 +790,47 @@ static int launch_model_width(const ModelArgs &a, bool narrow, hipStream_t st)
 
 #include "ba_server.h"
 
+// Device scratch of ba_generate_static: the degree pipeline's workspace for
+// callers that cannot allocate.  Each device holds its own copy from the
+// moment the library's code is loaded on it until the process ends.  In host
+// code `scratch` names a host-side stand-in, not the device copy: kernels get
+// the per-device address that static_scratch() takes from the runtime.
+static __device__ __align__(256) unsigned char scratch[BA_STATIC_SCRATCH_BYTES];
+
+namespace ba {
+
+// Partition blocks of a pass through the static scratch.  Fixed, so the
+// host decides before any device call whether a graph fits (BA_ENOMEM), and
+// small, since every (block, sub-bucket) region costs its slack in the
+// layout; MI355X has 256 compute units, one partition block each.
+constexpr uint32_t kStaticPBlocks = 256;
+
+static std::mutex g_scratch_mu;
+static std::atomic<void *> g_scratch_addr[kMaxDevices];
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device (with that device current) and kept.
+static int static_scratch(void **out)
+{
+    int slot = 0;
+    int rc = current_device_slot(&slot);
+    if (rc) return rc;
+    void *p = g_scratch_addr[slot].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        p = g_scratch_addr[slot].load(std::memory_order_relaxed);
+        if (!p) {
+            if ((rc = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))))) return rc;
+            if (!p || ((uintptr_t)p & 255)) return BA_EDEVICE;
+            g_scratch_addr[slot].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return BA_OK;
+}
+
+}  // namespace ba
+
 using namespace ba;
 
 extern "C" {
@@ -833,11 +878,31 @@ int ba_generate_ws(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint3
     graph_fits(n, d, &m);
     if (m && !edges) return BA_EINVAL;
     if (deg && m && (!workspace || ((uintptr_t)workspace & 255))) return BA_EINVAL;
-    if (deg && m && deg_piece(n, m, workspace_bytes) == 0) return BA_ENOMEM;
+    if (deg && m && deg_piece(n, m, workspace_bytes, kPBlocksMax) == 0) return BA_ENOMEM;
     hipStream_t st = (hipStream_t)stream;
     if ((rc = fill_first_endpoints_whole(n, d, deg, st))) return rc;
     if (deg) return gen_with_degrees(n, d, seed, 0, m, edges, deg, workspace, workspace_bytes, true, st);
     return launch_gen_u32(0, m, d, seed, edges, st);
+}
+
+int ba_generate_static(uint64_t n, uint32_t d, uint64_t seed, uint32_t *edges, uint32_t *deg, void *stream)
+{
+    uint64_t m = 0;
+    int rc = check_generate(n, d, 0, 0, edges, deg);
+    if (rc) return rc;
+    graph_fits(n, d, &m);
+    if (m && !edges) return BA_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (!deg || !m) {
+        if ((rc = fill_first_endpoints_whole(n, d, deg, st))) return rc;
+        return launch_gen_u32(0, m, d, seed, edges, st);
+    }
+    if (deg_piece(n, m, BA_STATIC_SCRATCH_BYTES, kStaticPBlocks) == 0) return BA_ENOMEM;
+    void *ws = nullptr;
+    if ((rc = static_scratch(&ws))) return rc;
+    if ((rc = fill_first_endpoints_whole(n, d, deg, st))) return rc;
+    return gen_with_degrees(n, d, seed, 0, m, edges, deg, ws, BA_STATIC_SCRATCH_BYTES, true, st, 1.0,
+                            kStaticPBlocks);
 }
 
 int ba_generate_range(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_begin, uint64_t edge_count,
@@ -860,7 +925,7 @@ int ba_generate_range_ws(uint64_t n, uint32_t d, uint64_t seed, uint64_t edge_be
     int rc = check_generate(n, d, edge_begin, edge_count, edges, deg);
     if (rc) return rc;
     if (deg && edge_count && (!workspace || ((uintptr_t)workspace & 255))) return BA_EINVAL;
-    if (deg && edge_count && deg_piece(n, edge_count, workspace_bytes) == 0) return BA_ENOMEM;
+    if (deg && edge_count && deg_piece(n, edge_count, workspace_bytes, kPBlocksMax) == 0) return BA_ENOMEM;
     hipStream_t st = (hipStream_t)stream;
     if (deg) {
         if ((rc = launch_first_endpoints<uint32_t>(deg, n, edge_begin, edge_count, d, n, st))) return rc;
@@ -879,7 +944,7 @@ int ba_test_generate_ws_scaled(uint64_t n, uint32_t d, uint64_t seed, uint32_t *
     if (rc) return rc;
     graph_fits(n, d, &m);
     if (m && (!edges || !workspace || ((uintptr_t)workspace & 255))) return BA_EINVAL;
-    if (m && deg_piece(n, m, workspace_bytes) == 0) return BA_ENOMEM;
+    if (m && deg_piece(n, m, workspace_bytes, kPBlocksMax) == 0) return BA_ENOMEM;
     hipStream_t st = (hipStream_t)stream;
     if ((rc = fill_first_endpoints_whole(n, d, deg, st))) return rc;
     return gen_with_degrees(n, d, seed, 0, m, edges, deg, workspace, workspace_bytes, true, st, cap_scale);

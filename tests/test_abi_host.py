@@ -261,3 +261,16 @@ def test_workspace_too_small_is_enomem_and_bad_pointers_einval():
     assert L.ba_generate_range_ws(n, d, 0, 5, 1 << 20, FAKE, FAKE, FAKE, 1000, None) == ba.BA_ENOMEM
     assert L.ba_generate_ws(n, d, 0, FAKE, FAKE, None, need, None) == ba.BA_EINVAL
     assert L.ba_generate_ws(n, d, 0, FAKE, FAKE, FAKE + 4, need, None) == ba.BA_EINVAL
+
+
+def test_static_scratch_too_small_is_enomem_before_any_device_call():
+    # n = 2^28 needs more than the static scratch for a single 2^20-edge pass
+    # (every region of its 8192 sub-buckets costs slack); without deg no
+    # scratch is used, and argument errors come first
+    L = ba.lib()
+    assert L.ba_generate_static(1 << 28, 1, 0, FAKE, FAKE, None) == ba.BA_ENOMEM
+    assert L.ba_generate_static(240_000_000, 2, 0, FAKE, FAKE, None) == ba.BA_ENOMEM
+    assert L.ba_generate_static(1, 1 << 31, 0, FAKE, FAKE, None) == ba.BA_ERANGE
+    assert L.ba_generate_static(10, 2, 0, None, FAKE, None) == ba.BA_EINVAL
+    assert L.ba_generate_static(10, 2, 0, FAKE, FAKE + 2, None) == ba.BA_EINVAL
+    assert L.ba_generate_static(0, 4, 0, None, None, None) == ba.BA_OK
