@@ -381,6 +381,7 @@ __global__ __launch_bounds__(kGenBlock) void k_gen_u32(GenArgs a)
 
 }  // namespace ba
 
+#include "ba_genpart.h"
 #include "ba_batch.h"
 #include "ba_model.h"
 
@@ -594,6 +595,29 @@ static uint64_t deg_piece(uint64_t n, uint64_t count, uint64_t ws_bytes, uint32_
     return lo / kPChunk * kPChunk;
 }
 
+// Totals, part scan and histograms of a pass whose partition has run, then
+// (unfused pipeline only) the targets after the partition's last whole chunk.
+static int deg_count(const DegArgs &a, uint64_t count, hipStream_t st)
+{
+    int rc;
+    if ((rc = launch_timed(BA_KT_OTHER, st,
+                           [&] { hipLaunchKernelGGL(k_deg_tot, dim3(a.p.NBsub), dim3(256), 0, st, a); })))
+        return rc;
+    if ((rc = launch_timed(BA_KT_OTHER, st, [&] { hipLaunchKernelGGL(k_deg_scan, dim3(1), dim3(1024), 0, st, a); })))
+        return rc;
+    const uint32_t parts_max = (uint32_t)((uint64_t)a.p.NBsub + (count + kHPart - 1) / kHPart + 1);
+    if ((rc = launch_timed(BA_KT_HIST, st,
+                           [&] { hipLaunchKernelGGL(k_deg_hist, dim3(parts_max), dim3(kHBlock), 0, st, a); })))
+        return rc;
+    // the tail's atomics after the histogram, which may store single-part counts directly
+    if (!a.p.fused && count % kPChunk) {
+        const uint32_t tb = (uint32_t)((count % kPChunk + 255) / 256);
+        if ((rc = launch_timed(BA_KT_OTHER, st, [&] { hipLaunchKernelGGL(k_deg_tail, dim3(tb), dim3(256), 0, st, a); })))
+            return rc;
+    }
+    return BA_OK;
+}
+
 // Second endpoints of edges begin .. begin+count-1 (the target list the
 // generator left in the workspace) added to deg: partition, totals, part
 // scan, histograms.  First endpoints are the caller's (a fill of d or the
@@ -621,22 +645,54 @@ static int degrees_of_targets(uint64_t n, uint32_t d, uint64_t begin, uint64_t c
                                [&] { hipLaunchKernelGGL(k_deg_part, dim3(P), dim3(kPBlock), 0, st, a); })))
             return rc;
     }
-    if ((rc = launch_timed(BA_KT_OTHER, st,
-                           [&] { hipLaunchKernelGGL(k_deg_tot, dim3(a.p.NBsub), dim3(256), 0, st, a); })))
-        return rc;
-    if ((rc = launch_timed(BA_KT_OTHER, st, [&] { hipLaunchKernelGGL(k_deg_scan, dim3(1), dim3(1024), 0, st, a); })))
-        return rc;
-    const uint32_t parts_max = (uint32_t)((uint64_t)a.p.NBsub + (count + kHPart - 1) / kHPart + 1);
-    if ((rc = launch_timed(BA_KT_HIST, st,
-                           [&] { hipLaunchKernelGGL(k_deg_hist, dim3(parts_max), dim3(kHBlock), 0, st, a); })))
-        return rc;
-    // the tail's atomics after the histogram, which may store single-part counts directly
-    if (count % kPChunk) {
-        const uint32_t tb = (uint32_t)((count % kPChunk + 255) / 256);
-        if ((rc = launch_timed(BA_KT_OTHER, st, [&] { hipLaunchKernelGGL(k_deg_tail, dim3(tb), dim3(256), 0, st, a); })))
+    return deg_count(a, count, st);
+}
+
+// One pass of the fused pipeline (graphs with one window of sub-buckets):
+// k_gen_part writes edges begin .. begin+count-1 and partitions their second
+// endpoints, then the histograms add them to deg.
+static int gen_part_pass(uint64_t n, uint32_t d, uint64_t seed, uint64_t begin, uint64_t count, uint32_t *edges,
+                         uint32_t *deg, void *ws, bool fresh, double cap_scale, uint32_t pmax, hipStream_t st)
+{
+    GenPartArgs ga{};
+    ga.g.key = make_hash_key(seed);
+    ga.g.div = make_divider(d);
+    ga.g.begin = begin;
+    ga.g.count = count;
+    ga.g.ntiles = (count + kFChunk - 1) / kFChunk;
+    ga.g.d = d;
+    ga.g.edges = edges;
+    ga.nchunks = ga.g.ntiles;
+    auto run = [&](auto kern) -> int {
+        uint32_t P = 0;
+        int rc = persistent_grid(kern, kFBlock, &P);
+        if (rc) return rc;
+        if (P > pmax) P = pmax;
+        DegArgs &q = ga.p;
+        q.p = make_deg_plan(n, count, P);
+        q.B = begin;
+        q.d = d;
+        q.deg = deg;
+        q.ws = (unsigned char *)ws;
+        q.scale = cap_scale;
+        q.fresh = fresh ? 1u : 0u;
+        q.g0 = 0;
+        if ((rc = launch_timed(BA_KT_OTHER, st,
+                               [&] { hipLaunchKernelGGL(k_deg_plan, dim3(1), dim3(1024), 0, st, q); })))
             return rc;
+        if ((rc = launch_timed(BA_KT_GEN, st, [&] { hipLaunchKernelGGL(kern, dim3(P), dim3(kFBlock), 0, st, ga); })))
+            return rc;
+        return deg_count(q, count, st);
+    };
+    const bool narrow = 2 * (begin + count) <= ((uint64_t)1 << 32);
+    const bool vec16 = ((uintptr_t)edges & 15) == 0;
+    const bool pow2 = ga.g.div.pow2 != 0;
+    if (narrow) {
+        if (pow2) return vec16 ? run(k_gen_part<true, true, true>) : run(k_gen_part<true, true, false>);
+        return vec16 ? run(k_gen_part<true, false, true>) : run(k_gen_part<true, false, false>);
     }
-    return BA_OK;
+    if (pow2) return vec16 ? run(k_gen_part<false, true, true>) : run(k_gen_part<false, true, false>);
+    return vec16 ? run(k_gen_part<false, false, true>) : run(k_gen_part<false, false, false>);
 }
 
 // Edges [begin, begin+count) written to `edges`, their second endpoints
@@ -653,10 +709,15 @@ static int gen_with_degrees(uint64_t n, uint32_t d, uint64_t seed, uint64_t begi
     for (uint64_t done = 0; done < count; done += piece) {
         const uint64_t C = count - done < piece ? count - done : piece;
         const DegPlan p = make_deg_plan(n, C, pmax);
-        int rc = launch_gen_u32(begin + done, C, d, seed, edges + 2 * done, st,
+        int rc;
+        if (p.fused) {
+            rc = gen_part_pass(n, d, seed, begin + done, C, edges + 2 * done, deg, ws, fresh && done == 0, cap_scale,
+                               pmax, st);
+        } else {
+            rc = launch_gen_u32(begin + done, C, d, seed, edges + 2 * done, st,
                                 (uint32_t *)((unsigned char *)ws + p.o_V));
-        if (rc) return rc;
-        rc = degrees_of_targets(n, d, begin + done, C, deg, ws, fresh && done == 0, cap_scale, pmax, st);
+            if (!rc) rc = degrees_of_targets(n, d, begin + done, C, deg, ws, fresh && done == 0, cap_scale, pmax, st);
+        }
         if (rc) return rc;
     }
     return BA_OK;

@@ -43,9 +43,12 @@
 
 namespace ba {
 
-constexpr uint32_t kS2 = 15;                    // sub-bucket width: 32768 nodes
+constexpr uint32_t kS2 = 15;                    // sub-bucket width of the partition kernel: 32768 nodes
 constexpr uint32_t kSub = 1u << kS2;
 constexpr uint32_t kWin = 2048;                 // sub-buckets per partition window
+constexpr uint32_t kS16 = 16;                   // sub-bucket width of the fused generator: 65536 nodes
+constexpr uint32_t kSub16 = 1u << kS16;
+constexpr uint32_t kWin16 = 1024;               // its sub-buckets (one window: n <= 2^26)
 constexpr uint32_t kPBlock = 1024;
 constexpr uint32_t kPPer = 20;                  // edges per thread per chunk
 constexpr uint32_t kPChunk = kPBlock * kPPer;   // 20480 edges per chunk
@@ -96,6 +99,9 @@ __host__ __device__ inline uint32_t region_cap(double M, uint32_t P)
 // partitioned by at most P blocks.
 struct DegPlan {
     uint32_t NBsub, NW, P;
+    uint32_t fused;  // n <= 2^26: the generator partitions its own targets into 65536-node sub-buckets
+                     // (no target list); else the partition kernel, 32768-node sub-buckets in windows
+    uint32_t S;      // sub-bucket shift: 16 (fused) or 15
     uint64_t n, C;
     uint64_t A;  // region entries reserved in the layout
     uint64_t o_V, o_rcap, o_off, o_fill, o_tot, o_parts, o_partoff, o_flag, o_L, bytes;
@@ -109,14 +115,16 @@ static inline DegPlan make_deg_plan(uint64_t n, uint64_t C, uint32_t P)
     p.n = n;
     p.C = C;
     p.P = P;
-    p.NBsub = (uint32_t)((n + kSub - 1) >> kS2);
+    p.fused = n <= ((uint64_t)kWin << kS2) ? 1u : 0u;
+    p.S = kS2;
+    p.NBsub = (uint32_t)((n + ((uint64_t)1 << p.S) - 1) >> p.S);
     if (p.NBsub == 0) p.NBsub = 1;
-    p.NW = (p.NBsub + kWin - 1) / kWin;
+    p.NW = p.fused ? 1u : (p.NBsub + kWin - 1) / kWin;
     // sum of region_cap over sub-buckets and blocks is at most
     //   1.15 C + 8 sqrt(P NBsub C) + 64 P NBsub  (Cauchy-Schwarz), plus rounding
     p.A = C + C / 6 + 8 * isqrt_u64((uint64_t)P * p.NBsub * C) + 8 + 65ull * P * p.NBsub;
     uint64_t o = 0;
-    p.o_V = o; o = align256(o + 4 * C);
+    p.o_V = o; o = align256(o + (p.fused ? 0 : 4 * C));
     p.o_rcap = o; o = align256(o + 4ull * p.NBsub);
     p.o_off = o; o = align256(o + 8ull * p.NBsub);
     p.o_fill = o; o = align256(o + 4ull * P * p.NBsub);
@@ -202,8 +210,8 @@ __global__ __launch_bounds__(1024) void k_deg_plan(DegArgs a)
         uint64_t x = 0;
         uint32_t cap = 0;
         if (g < N) {
-            const double lo = (double)((uint64_t)g << kS2);
-            const uint64_t hi = ((uint64_t)(g + 1) << kS2) < a.p.n ? ((uint64_t)(g + 1) << kS2) : a.p.n;
+            const double lo = (double)((uint64_t)g << a.p.S);
+            const uint64_t hi = ((uint64_t)(g + 1) << a.p.S) < a.p.n ? ((uint64_t)(g + 1) << a.p.S) : a.p.n;
             const double M = N == 1 ? (double)a.p.C : expected_bucket_mass(a.d, a.B, a.p.C, lo, (double)hi);
             cap = (uint32_t)((double)region_cap(M, a.p.P) * a.scale);
             x = (uint64_t)cap * a.p.P;

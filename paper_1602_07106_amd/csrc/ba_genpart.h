@@ -1,0 +1,198 @@
+// ba_genpart.h -- the stored generator with the degree pipeline's partition
+// fused in, for graphs whose 32768-node sub-buckets fit one partition window
+// (n <= 2^26).
+//
+// One block of 16 waves per compute unit takes chunks of kFChunk consecutive
+// edge IDs.  Each wave runs the chain loop (paper Section 2, figure
+// generateEdge) over its kFTile edges into its part of the block's LDS stage,
+// writes the edge pairs as the plain generator does, and keeps the second
+// endpoints of its edges in registers (22 a lane).  The block then
+// counting-sorts the chunk's second endpoints by sub-bucket in the same LDS
+// (the stage is free again) and appends each sub-bucket's run of 16-bit local
+// indices to the block's own region for it, exactly the layout k_deg_part
+// builds from the target list; the totals, scan and histogram kernels of
+// ba_degree.h then finish the degrees.  No target list is written or read.
+//
+// Chunk size is what matters for the sort: a chunk's 22528 second endpoints
+// over 2048 sub-buckets leave runs of about 11 entries (22 bytes) per region
+// and chunk, and shorter runs cost more in scattered stores than the
+// overlap of two smaller blocks per compute unit gains.
+#pragma once
+
+namespace ba {
+
+constexpr uint32_t kFWaves = 16;
+constexpr uint32_t kFBlock = kFWaves * kWave;   // 1024 threads, one block per compute unit (120 KiB of LDS)
+constexpr uint32_t kFTile = 1408;               // edges per wave per chunk (a multiple of 128)
+constexpr uint32_t kFChunk = kFWaves * kFTile;  // 22528 edges per block chunk
+constexpr uint32_t kFPer = kFTile / kWave;      // second endpoints per thread
+constexpr uint32_t kFBins = kWin / kFBlock;     // sub-buckets per thread in the scan
+static_assert(kFTile % (2 * kWave) == 0 && kFPer % 2 == 0, "pair flush");
+static_assert(kFChunk < 65536, "16-bit ranks");
+
+struct GenPartArgs {
+    GenArgs g;         // chain loop and edge output: edges g.begin .. g.begin+g.count-1
+    DegArgs p;         // partition layout: one window (g0 = 0), P = the grid
+    uint64_t nchunks;  // ceil(g.count / kFChunk)
+};
+
+template <bool NARROW, bool POW2, bool VEC16>
+__global__ __launch_bounds__(kFBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_gen_part(GenPartArgs a)
+{
+    constexpr uint32_t kOut = kWin << kS2;  // no entry (past the launch's edges): lane-private dummy bins
+    __shared__ uint32_t stage[kFChunk];     // chain results, then the chunk's second endpoints in sorted order
+    __shared__ uint32_t cnt[kWin + 64];     // per chunk: counts, then run starts
+    __shared__ uint32_t wpos[kWin];         // next slot of this block's region per sub-bucket (<= wend)
+    __shared__ uint32_t wend[kWin];         // end of this block's region per sub-bucket
+    __shared__ uint32_t dlx[kWin];          // per chunk: region slot of sorted entry x is dlx[b] + x
+    __shared__ uint32_t scan_sh[16];
+    __shared__ uint32_t any_over;           // per chunk: some region of this block is full
+    const DegArgs &q = a.p;
+    const uint32_t nb = q.p.NBsub;  // <= kWin
+    const uint32_t blk = blockIdx.x, P = gridDim.x;
+    for (uint32_t b = threadIdx.x; b < kWin; b += kFBlock) {
+        const uint32_t cp = b < nb ? ws_rcap(q)[b] : 0u;
+        const uint32_t base = b < nb ? (uint32_t)(ws_off(q)[b] + (uint64_t)blk * cp) : 0u;
+        wpos[b] = base;
+        wend[b] = base + cp;
+    }
+    uint16_t *L = ws_L(q);
+    const uint32_t lane = __lane_id();
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform: scalar tile bases
+    uint32_t *st_w = stage + wv * kFTile;
+
+    for (uint64_t ch = blk; ch < a.nchunks; ch += P) {
+        // ---- this wave's edges of the chunk: chain loop, edge pairs out
+        const uint64_t woff = ch * kFChunk + (uint64_t)wv * kFTile;
+        const uint32_t tn = woff < a.g.count ? (uint32_t)min((uint64_t)kFTile, a.g.count - woff) : 0u;
+        const uint64_t ibase = a.g.begin + woff;
+        uint32_t v[kFPer];
+#pragma unroll
+        for (uint32_t t = 0; t < kFPer; t++) v[t] = kOut;
+        if (tn) {
+            if constexpr (NARROW)
+                chain_tile(st_w, tn, lane, (uint32_t)(2 * ibase + 1),
+                           [&](uint32_t r) { return hash_narrow(r, a.g.key); }, [](uint32_t r) { return r; });
+            else
+                chain_tile(st_w, tn, lane, 2 * ibase + 1, [&](uint64_t r) { return hash_wide(r, a.g.key); },
+                           [&](uint64_t r) { return (uint32_t)fdiv64<POW2>(r >> 1, a.g.div); });
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            uint32_t *out = a.g.edges + 2 * woff;
+            if (tn == kFTile) {
+#pragma unroll
+                for (uint32_t t = 0; t < kFPer / 2; t++) {
+                    const uint32_t j = 2 * lane + t * (2 * kWave);
+                    uint32_t u0, u1, v0, v1;
+                    flush_pair<NARROW, POW2>(a.g, st_w, ibase, j, u0, u1, v0, v1);
+                    if constexpr (VEC16)
+                        *reinterpret_cast<uint4 *>(out + 2 * j) = make_uint4(u0, v0, u1, v1);
+                    else
+                        store_pair<false>(out, j, kFTile, u0, v0, u1, v1);
+                    v[2 * t] = v0;
+                    v[2 * t + 1] = v1;
+                }
+            } else {
+#pragma unroll
+                for (uint32_t t = 0; t < kFPer / 2; t++) {
+                    const uint32_t j = 2 * lane + t * (2 * kWave);
+                    if (j < tn) {
+                        uint32_t u0, u1, v0, v1;
+                        flush_pair<NARROW, POW2>(a.g, st_w, ibase, j, u0, u1, v0, v1);
+                        store_pair<VEC16>(out, j, tn, u0, v0, u1, v1);
+                        v[2 * t] = v0;
+                        if (j + 1 < tn) v[2 * t + 1] = v1;
+                    }
+                }
+            }
+        }
+
+        // ---- the chunk's second endpoints: counting sort by sub-bucket
+        for (uint32_t b = threadIdx.x; b < kWin + 64; b += kFBlock) cnt[b] = 0;
+        lds_barrier();  // also: every wave has read its stage part
+        // counts; each entry keeps its rank in its bin, two 16-bit ranks a register
+        uint32_t rk[kFPer / 2];
+#pragma unroll
+        for (uint32_t t = 0; t < kFPer; t += 2) {
+            const uint32_t b0 = (v[t] >> kS2) + (v[t] == kOut ? lane : 0u);
+            const uint32_t b1 = (v[t + 1] >> kS2) + (v[t + 1] == kOut ? lane : 0u);
+            const uint32_t r0 = atomicAdd(&cnt[b0], 1u);
+            const uint32_t r1 = atomicAdd(&cnt[b1], 1u);
+            rk[t / 2] = (r0 & 0xFFFFu) | (r1 << 16);
+        }
+        if (threadIdx.x == 0) any_over = 0;
+        lds_barrier();
+        // run starts (exclusive scan, kFBins sub-buckets a thread) and region slots
+        uint32_t c[kFBins], sum = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kFBins; k++) {
+            c[k] = cnt[kFBins * threadIdx.x + k];
+            sum += c[k];
+        }
+        uint32_t total;
+        uint32_t s = block_exclusive_scan<uint32_t>(sum, scan_sh, &total);
+#pragma unroll
+        for (uint32_t k = 0; k < kFBins; k++) {
+            const uint32_t b = kFBins * threadIdx.x + k;
+            if (c[k]) {
+                const uint32_t w = wpos[b], e = wend[b];
+                const uint32_t room = e - w;
+                dlx[b] = w - s;  // mod 2^32: dlx + x is the slot for x in [s, s + c)
+                wpos[b] = c[k] < room ? w + c[k] : e;
+                if (c[k] > room) any_over = 1;
+            }
+            cnt[b] = s;
+            s += c[k];
+        }
+        lds_barrier();
+        // scatter into sorted order: run start + rank (cnt[kWin] for no entry, never stored)
+#pragma unroll
+        for (uint32_t t0 = 0; t0 < kFPer; t0 += kFPer / 2) {
+            uint32_t sb[kFPer / 2];
+#pragma unroll
+            for (uint32_t j = 0; j < kFPer / 2; j++) sb[j] = cnt[v[t0 + j] >> kS2];
+#pragma unroll
+            for (uint32_t j = 0; j < kFPer / 2; j++) {
+                const uint32_t t = t0 + j;
+                if (v[t] != kOut) stage[sb[j] + ((rk[t / 2] >> (16 * (t & 1))) & 0xFFFFu)] = v[t];
+            }
+        }
+        lds_barrier();
+        // sorted runs out: consecutive threads take consecutive sorted entries,
+        // so a store covers a few runs of contiguous region slots
+        const bool over = any_over != 0;
+        for (uint32_t x0 = threadIdx.x; x0 < total; x0 += 4 * kFBlock) {
+            uint32_t w[4], t[4];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; u++) w[u] = x0 + u * kFBlock < total ? stage[x0 + u * kFBlock] : 0u;
+#pragma unroll
+            for (uint32_t u = 0; u < 4; u++) t[u] = dlx[w[u] >> kS2];
+            if (!over) {  // no region full in this chunk (the normal case)
+#pragma unroll
+                for (uint32_t u = 0; u < 4; u++)
+                    if (x0 + u * kFBlock < total) L[t[u] + x0 + u * kFBlock] = (uint16_t)(w[u] & (kSub - 1));
+            } else {
+                if (x0 == 0) *ws_flag(q) = 1;  // deg takes atomics before the histogram
+#pragma unroll
+                for (uint32_t u = 0; u < 4; u++) {
+                    const uint32_t x = x0 + u * kFBlock;
+                    if (x < total) {
+                        const uint32_t slot = t[u] + x;
+                        if (slot < wend[w[u] >> kS2])
+                            L[slot] = (uint16_t)(w[u] & (kSub - 1));
+                        else
+                            deg_atomic_add(q.deg, w[u], 1u);
+                    }
+                }
+            }
+        }
+        lds_barrier();  // the stage is free for the next chunk's chain loop
+    }
+    // this block's fill per sub-bucket (k_deg_tot caps it at the region size)
+    uint32_t *gfill = ws_fill(q) + (uint64_t)blk * nb;
+    for (uint32_t b = threadIdx.x; b < nb; b += kFBlock)
+        gfill[b] = wpos[b] - (uint32_t)(ws_off(q)[b] + (uint64_t)blk * ws_rcap(q)[b]);
+}
+
+}  // namespace ba

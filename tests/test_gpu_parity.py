@@ -341,3 +341,41 @@ def test_range_degrees_starting_and_ending_inside_a_node():
         assert np.array_equal(_u32(out), E[2 * b:2 * (b + c)])
         ref = np.bincount(E[2 * b:2 * (b + c)].astype(np.int64), minlength=n)
         assert np.array_equal(_u32(deg).astype(np.int64), ref)
+
+
+def test_degrees_past_one_window_take_the_partition_kernel():
+    # n just above 2^26: 2049 sub-buckets of 32768 nodes, two windows, so the
+    # generator writes the target list and the partition kernel sorts it
+    n, d, seed = (1 << 26) + 12345, 2, 19
+    _say("unfused pipeline", n, d, seed)
+    edges, deg = ba.generate(n, d, seed, degrees=True)
+    torch.cuda.synchronize()
+    E, _ = oracle.bb_generate(n, d, seed)
+    assert np.array_equal(_u32(edges), E)
+    assert np.array_equal(_u32(deg).astype(np.uint64), oracle.count_degrees(E, n))
+
+
+def test_fused_degrees_on_wide_positions_and_misaligned_output():
+    # n <= 2^26 with positions beyond 2^32 (the fused kernel's 64-bit hash),
+    # a range across edge 2^31 with accumulated degrees; then a graph whose
+    # edge buffer is only 4-byte aligned (the fused kernel's scalar stores)
+    n, d, seed = 1 << 21, 1100, 5
+    b, c = (1 << 31) - 777777, 1555555
+    _say("fused wide range", n, d, seed, b, c)
+    deg = torch.zeros(n, dtype=torch.int32, device="cuda")
+    ws = ba.workspace(n, d, c)
+    out = ba.generate_range(n, d, seed, b, c, deg=deg, ws=ws)
+    torch.cuda.synchronize()
+    ref, _ = oracle.edges_range(d, seed, b, c)
+    ref = ref.astype(np.uint32).reshape(-1)
+    assert np.array_equal(_u32(out), ref)
+    assert np.array_equal(_u32(deg).astype(np.int64), np.bincount(ref.astype(np.int64), minlength=n))
+    n, d, seed = 200003, 7, 31
+    _say("fused misaligned", n, d, seed)
+    E, _ = oracle.bb_generate(n, d, seed)
+    buf = torch.full((2 * n * d + 1,), -1, dtype=torch.int32, device="cuda")
+    view = buf[1:]
+    _, deg2 = ba.generate(n, d, seed, degrees=True, out=view)
+    torch.cuda.synchronize()
+    assert np.array_equal(_u32(view), E)
+    assert np.array_equal(_u32(deg2).astype(np.uint64), oracle.count_degrees(E, n))
