@@ -606,8 +606,12 @@ static int deg_count(const DegArgs &a, uint64_t count, hipStream_t st)
     if ((rc = launch_timed(BA_KT_OTHER, st, [&] { hipLaunchKernelGGL(k_deg_scan, dim3(1), dim3(1024), 0, st, a); })))
         return rc;
     const uint32_t parts_max = (uint32_t)((uint64_t)a.p.NBsub + (count + kHPart - 1) / kHPart + 1);
-    if ((rc = launch_timed(BA_KT_HIST, st,
-                           [&] { hipLaunchKernelGGL(k_deg_hist, dim3(parts_max), dim3(kHBlock), 0, st, a); })))
+    if ((rc = launch_timed(BA_KT_HIST, st, [&] {
+             if (a.p.S == kS16)
+                 hipLaunchKernelGGL(k_deg_hist16, dim3(parts_max), dim3(kHBlock), 0, st, a);
+             else
+                 hipLaunchKernelGGL(k_deg_hist, dim3(parts_max), dim3(kHBlock), 0, st, a);
+         })))
         return rc;
     // the tail's atomics after the histogram, which may store single-part counts directly
     if (!a.p.fused && count % kPChunk) {

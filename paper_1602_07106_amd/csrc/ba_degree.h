@@ -115,8 +115,8 @@ static inline DegPlan make_deg_plan(uint64_t n, uint64_t C, uint32_t P)
     p.n = n;
     p.C = C;
     p.P = P;
-    p.fused = n <= ((uint64_t)kWin << kS2) ? 1u : 0u;
-    p.S = kS2;
+    p.fused = n <= ((uint64_t)kWin16 << kS16) ? 1u : 0u;
+    p.S = p.fused ? kS16 : kS2;
     p.NBsub = (uint32_t)((n + ((uint64_t)1 << p.S) - 1) >> p.S);
     if (p.NBsub == 0) p.NBsub = 1;
     p.NW = p.fused ? 1u : (p.NBsub + kWin - 1) / kWin;
@@ -419,66 +419,90 @@ __global__ __launch_bounds__(1024) void k_deg_scan(DegArgs a)
 
 // H: one block per part (sub-bucket g, the regions of a contiguous range of
 // partition blocks): LDS histogram, then the counts go to deg.
-__global__ __launch_bounds__(kHBlock) void k_deg_hist(DegArgs a)
+// The part of histogram block k: sub-bucket g, its number of parts np and the
+// partition blocks p0 .. p1-1 whose regions the part holds; false past the
+// last part.
+struct HistPart {
+    uint32_t g, np, p0, p1;
+};
+__device__ __forceinline__ bool hist_part(const DegArgs &a, uint32_t k, HistPart &h)
 {
-    __shared__ uint32_t cnt[kSub];
     const uint32_t N = a.p.NBsub;
     const uint32_t *poff = ws_partoff(a);
-    const uint32_t k = blockIdx.x;
-    if (k >= poff[N]) return;
+    if (k >= poff[N]) return false;
     uint32_t lo = 0, hi = N;  // sub-bucket g with poff[g] <= k < poff[g+1]
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) / 2;
         if (poff[mid] <= k) lo = mid; else hi = mid;
     }
-    const uint32_t g = lo;
-    const uint32_t np = ws_parts(a)[g], j = k - poff[g];
-    const uint32_t P = a.p.P;
-    const uint32_t p0 = (uint32_t)((uint64_t)P * j / np), p1 = (uint32_t)((uint64_t)P * (j + 1) / np);
+    h.g = lo;
+    h.np = ws_parts(a)[lo];
+    const uint32_t j = k - poff[lo], P = a.p.P;
+    h.p0 = (uint32_t)((uint64_t)P * j / h.np);
+    h.p1 = (uint32_t)((uint64_t)P * (j + 1) / h.np);
+    return true;
+}
+
+// Calls f(x) for every entry x (a 16-bit local index) of the regions the
+// calling wave takes of a part: regions p0 + wv, p0 + wv + 16, ...  Lane j
+// fetches the fill of the wave's j-th region up front (at most kPBlocksMax /
+// 16 = 64 regions a wave), so no region waits on a load of its own length;
+// 8 entries per 16-byte load where aligned, four loads in flight per lane
+// before their entries are visited.  Returns the wave's entry count.
+template <class F>
+__device__ __forceinline__ uint32_t hist_visit(const DegArgs &a, const HistPart &h, F f)
+{
+    static_assert(kPBlocksMax / (kHBlock / 64) <= 64, "one region fill per lane");
+    const uint32_t N = a.p.NBsub, g = h.g;
     const uint32_t cp = ws_rcap(a)[g];
     const uint64_t base = ws_off(a)[g];
     const uint32_t *fill = ws_fill(a);
     const uint16_t *L = ws_L(a);
-
-    for (uint32_t x = threadIdx.x; x < kSub; x += kHBlock) cnt[x] = 0;
-    __syncthreads();
-    // each wave takes whole regions (p0 + wv, p0 + wv + 16, ...); lane j
-    // fetches the fill of the wave's j-th region up front (at most
-    // kPBlocksMax / 16 = 64 regions a wave), so no region waits on a load of
-    // its own length; 8 entries per 16-byte load where aligned
-    static_assert(kPBlocksMax / (kHBlock / 64) <= 64, "one region fill per lane");
     const uint32_t lane = __lane_id(), wv = threadIdx.x / 64;
-    const uint32_t pl = p0 + wv + (kHBlock / 64) * lane;
-    const uint32_t nl = pl < p1 ? min(fill[(uint64_t)pl * N + g], cp) : 0u;
-    for (uint32_t p = p0 + wv, jr = 0; p < p1; p += kHBlock / 64, jr++) {
+    const uint32_t pl = h.p0 + wv + (kHBlock / 64) * lane;
+    const uint32_t nl = pl < h.p1 ? min(fill[(uint64_t)pl * N + g], cp) : 0u;
+    uint32_t total = 0;
+    for (uint32_t p = h.p0 + wv, jr = 0; p < h.p1; p += kHBlock / 64, jr++) {
         const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)nl, (int)jr);  // jr is wave-uniform
+        total += n;
         const uint16_t *src = L + base + (uint64_t)p * cp;
         const uint32_t head = min(n, (uint32_t)((8 - (((uintptr_t)src >> 1) & 7)) & 7));
-        if (lane < head) atomicAdd(&cnt[src[lane]], 1u);
+        if (lane < head) f((uint32_t)src[lane]);
         const uint32_t nv = (n - head) / 8;
         const uint4 *vs = reinterpret_cast<const uint4 *>(src + head);
-        auto count8 = [&](const uint4 &q) {
-            atomicAdd(&cnt[q.x & 0xFFFFu], 1u);
-            atomicAdd(&cnt[q.x >> 16], 1u);
-            atomicAdd(&cnt[q.y & 0xFFFFu], 1u);
-            atomicAdd(&cnt[q.y >> 16], 1u);
-            atomicAdd(&cnt[q.z & 0xFFFFu], 1u);
-            atomicAdd(&cnt[q.z >> 16], 1u);
-            atomicAdd(&cnt[q.w & 0xFFFFu], 1u);
-            atomicAdd(&cnt[q.w >> 16], 1u);
+        auto visit8 = [&](const uint4 &q) {
+            f(q.x & 0xFFFFu);
+            f(q.x >> 16);
+            f(q.y & 0xFFFFu);
+            f(q.y >> 16);
+            f(q.z & 0xFFFFu);
+            f(q.z >> 16);
+            f(q.w & 0xFFFFu);
+            f(q.w >> 16);
         };
-        // four 16-byte loads in flight per lane before their 32 atomics
         uint32_t t = lane;
         for (; t + 192 < nv; t += 256) {
             const uint4 q0 = vs[t], q1 = vs[t + 64], q2 = vs[t + 128], q3 = vs[t + 192];
-            count8(q0);
-            count8(q1);
-            count8(q2);
-            count8(q3);
+            visit8(q0);
+            visit8(q1);
+            visit8(q2);
+            visit8(q3);
         }
-        for (; t < nv; t += 64) count8(vs[t]);
-        for (uint32_t x = head + nv * 8 + lane; x < n; x += 64) atomicAdd(&cnt[src[x]], 1u);
+        for (; t < nv; t += 64) visit8(vs[t]);
+        for (uint32_t x = head + nv * 8 + lane; x < n; x += 64) f((uint32_t)src[x]);
     }
+    return total;
+}
+
+__global__ __launch_bounds__(kHBlock) void k_deg_hist(DegArgs a)
+{
+    __shared__ uint32_t cnt[kSub];
+    HistPart hp;
+    if (!hist_part(a, blockIdx.x, hp)) return;
+    const uint32_t g = hp.g, np = hp.np;
+    for (uint32_t x = threadIdx.x; x < kSub; x += kHBlock) cnt[x] = 0;
+    __syncthreads();
+    hist_visit(a, hp, [&](uint32_t x) { atomicAdd(&cnt[x], 1u); });
     __syncthreads();
     const uint64_t vbase = (uint64_t)g << kS2;
     // deg[v] = d before this block for a single-part sub-bucket of a fresh
@@ -507,6 +531,77 @@ __global__ __launch_bounds__(kHBlock) void k_deg_hist(DegArgs a)
 #pragma unroll
             for (uint32_t u = 0; u < 8; u++)
                 if (c[u]) deg_atomic_add(a.deg, vbase + y0 + u * kHBlock, c[u]);
+        }
+    }
+}
+
+// H for the fused generator's 65536-node sub-buckets: the same streaming of
+// a part's regions into an LDS histogram, with two 16-bit counters per LDS
+// word (128 KiB; node 2y in the low half of word y, 2y+1 in the high half).
+// Increments do not test for a wrap.  Instead the block sums its counters
+// afterwards: a wrap of a low half carries one into the high half and loses
+// 65536, a wrap of a high half loses 65536, so the sum equals the number of
+// entries counted exactly when no counter wrapped.  When one did (a node
+// with 65536 or more second endpoints in one part: never for the mean-field
+// degrees of realistic graphs, but possible for tiny n and huge d) the block
+// adds every entry of its part to deg by global atomics instead.
+__global__ __launch_bounds__(kHBlock) void k_deg_hist16(DegArgs a)
+{
+    constexpr uint32_t kWords = kSub16 / 2;
+    constexpr uint32_t kPer = kWords / kHBlock;  // counter words a thread writes back
+    __shared__ uint32_t cnt[kWords];
+    __shared__ uint32_t sh[16];
+    __shared__ uint32_t counted;
+    HistPart hp;
+    if (!hist_part(a, blockIdx.x, hp)) return;
+    for (uint32_t y = threadIdx.x; y < kWords; y += kHBlock) cnt[y] = 0;
+    if (threadIdx.x == 0) counted = 0;
+    __syncthreads();
+    const uint32_t mine = hist_visit(a, hp, [&](uint32_t x) { atomicAdd(&cnt[x >> 1], 1u << ((x & 1u) << 4)); });
+    if (__lane_id() == 0) atomicAdd(&counted, mine);  // mine is wave-uniform
+    __syncthreads();
+    uint32_t c[kPer], s = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kPer; u++) {
+        c[u] = cnt[threadIdx.x + u * kHBlock];
+        s += (c[u] & 0xFFFFu) + (c[u] >> 16);
+    }
+    uint32_t sum;
+    (void)block_exclusive_scan<uint32_t>(s, sh, &sum);
+    const uint64_t vbase = (uint64_t)hp.g << kS16;
+    if (sum != counted) {  // some counter wrapped: this part's entries by global atomics
+        hist_visit(a, hp, [&](uint32_t x) { deg_atomic_add(a.deg, vbase + x, 1u); });
+        return;
+    }
+    // deg[v] = d before this block for a single-part sub-bucket of a fresh
+    // pass with no region overflow
+    const bool direct = a.fresh && *ws_flag(a) == 0;
+    const uint64_t n = a.p.n;
+#pragma unroll
+    for (uint32_t u0 = 0; u0 < kPer; u0 += 8) {
+        uint32_t old[16];
+        if (hp.np == 1 && !direct) {  // plain read-modify-write, 16 reads in flight
+#pragma unroll
+            for (uint32_t u = 0; u < 8; u++) {
+                const uint64_t v = vbase + 2 * (threadIdx.x + (u0 + u) * kHBlock);
+                old[2 * u] = (c[u0 + u] & 0xFFFFu) && v < n ? a.deg[v] : 0u;
+                old[2 * u + 1] = (c[u0 + u] >> 16) && v + 1 < n ? a.deg[v + 1] : 0u;
+            }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 8; u++) {
+            const uint64_t v = vbase + 2 * (threadIdx.x + (u0 + u) * kHBlock);
+#pragma unroll
+            for (uint32_t h = 0; h < 2; h++) {
+                const uint32_t cv = h ? c[u0 + u] >> 16 : c[u0 + u] & 0xFFFFu;
+                if (!cv || v + h >= n) continue;
+                if (hp.np == 1 && direct)
+                    a.deg[v + h] = (uint32_t)a.d + cv;  // the only block of this sub-bucket: d + count, no read
+                else if (hp.np == 1)
+                    a.deg[v + h] = old[2 * u + h] + cv;
+                else
+                    deg_atomic_add(a.deg, v + h, cv);
+            }
         }
     }
 }

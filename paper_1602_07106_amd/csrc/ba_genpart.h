@@ -1,6 +1,6 @@
 // ba_genpart.h -- the stored generator with the degree pipeline's partition
-// fused in, for graphs whose 32768-node sub-buckets fit one partition window
-// (n <= 2^26).
+// fused in, for graphs of at most 2^26 nodes (1024 sub-buckets of 65536
+// nodes; their histograms are k_deg_hist16).
 //
 // One block of 16 waves per compute unit takes chunks of kFChunk consecutive
 // edge IDs.  Each wave runs the chain loop (paper Section 2, figure
@@ -13,10 +13,11 @@
 // builds from the target list; the totals, scan and histogram kernels of
 // ba_degree.h then finish the degrees.  No target list is written or read.
 //
-// Chunk size is what matters for the sort: a chunk's 22528 second endpoints
-// over 2048 sub-buckets leave runs of about 11 entries (22 bytes) per region
-// and chunk, and shorter runs cost more in scattered stores than the
-// overlap of two smaller blocks per compute unit gains.
+// Run length is what matters for the sort: a chunk's 22528 second endpoints
+// over 1024 sub-buckets leave runs of about 22 entries (44 bytes) per region
+// and chunk; shorter runs (smaller chunks, or 32768-node sub-buckets) cost
+// more in scattered stores than the overlap of two smaller blocks per
+// compute unit gains.
 #pragma once
 
 namespace ba {
@@ -26,9 +27,10 @@ constexpr uint32_t kFBlock = kFWaves * kWave;   // 1024 threads, one block per c
 constexpr uint32_t kFTile = 1408;               // edges per wave per chunk (a multiple of 128)
 constexpr uint32_t kFChunk = kFWaves * kFTile;  // 22528 edges per block chunk
 constexpr uint32_t kFPer = kFTile / kWave;      // second endpoints per thread
-constexpr uint32_t kFBins = kWin / kFBlock;     // sub-buckets per thread in the scan
+constexpr uint32_t kFBins = kWin16 / kFBlock;   // sub-buckets per thread in the scan
 static_assert(kFTile % (2 * kWave) == 0 && kFPer % 2 == 0, "pair flush");
 static_assert(kFChunk < 65536, "16-bit ranks");
+static_assert(kWin16 % kFBlock == 0, "scan");
 
 struct GenPartArgs {
     GenArgs g;         // chain loop and edge output: edges g.begin .. g.begin+g.count-1
@@ -39,18 +41,18 @@ struct GenPartArgs {
 template <bool NARROW, bool POW2, bool VEC16>
 __global__ __launch_bounds__(kFBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_gen_part(GenPartArgs a)
 {
-    constexpr uint32_t kOut = kWin << kS2;  // no entry (past the launch's edges): lane-private dummy bins
+    constexpr uint32_t kOut = kWin16 << kS16;  // no entry (past the launch's edges): lane-private dummy bins
     __shared__ uint32_t stage[kFChunk];     // chain results, then the chunk's second endpoints in sorted order
-    __shared__ uint32_t cnt[kWin + 64];     // per chunk: counts, then run starts
-    __shared__ uint32_t wpos[kWin];         // next slot of this block's region per sub-bucket (<= wend)
-    __shared__ uint32_t wend[kWin];         // end of this block's region per sub-bucket
-    __shared__ uint32_t dlx[kWin];          // per chunk: region slot of sorted entry x is dlx[b] + x
+    __shared__ uint32_t cnt[kWin16 + 64];     // per chunk: counts, then run starts
+    __shared__ uint32_t wpos[kWin16];         // next slot of this block's region per sub-bucket (<= wend)
+    __shared__ uint32_t wend[kWin16];         // end of this block's region per sub-bucket
+    __shared__ uint32_t dlx[kWin16];          // per chunk: region slot of sorted entry x is dlx[b] + x
     __shared__ uint32_t scan_sh[16];
     __shared__ uint32_t any_over;           // per chunk: some region of this block is full
     const DegArgs &q = a.p;
-    const uint32_t nb = q.p.NBsub;  // <= kWin
+    const uint32_t nb = q.p.NBsub;  // <= kWin16
     const uint32_t blk = blockIdx.x, P = gridDim.x;
-    for (uint32_t b = threadIdx.x; b < kWin; b += kFBlock) {
+    for (uint32_t b = threadIdx.x; b < kWin16; b += kFBlock) {
         const uint32_t cp = b < nb ? ws_rcap(q)[b] : 0u;
         const uint32_t base = b < nb ? (uint32_t)(ws_off(q)[b] + (uint64_t)blk * cp) : 0u;
         wpos[b] = base;
@@ -109,14 +111,14 @@ __global__ __launch_bounds__(kFBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
         }
 
         // ---- the chunk's second endpoints: counting sort by sub-bucket
-        for (uint32_t b = threadIdx.x; b < kWin + 64; b += kFBlock) cnt[b] = 0;
+        for (uint32_t b = threadIdx.x; b < kWin16 + 64; b += kFBlock) cnt[b] = 0;
         lds_barrier();  // also: every wave has read its stage part
         // counts; each entry keeps its rank in its bin, two 16-bit ranks a register
         uint32_t rk[kFPer / 2];
 #pragma unroll
         for (uint32_t t = 0; t < kFPer; t += 2) {
-            const uint32_t b0 = (v[t] >> kS2) + (v[t] == kOut ? lane : 0u);
-            const uint32_t b1 = (v[t + 1] >> kS2) + (v[t + 1] == kOut ? lane : 0u);
+            const uint32_t b0 = (v[t] >> kS16) + (v[t] == kOut ? lane : 0u);
+            const uint32_t b1 = (v[t + 1] >> kS16) + (v[t + 1] == kOut ? lane : 0u);
             const uint32_t r0 = atomicAdd(&cnt[b0], 1u);
             const uint32_t r1 = atomicAdd(&cnt[b1], 1u);
             rk[t / 2] = (r0 & 0xFFFFu) | (r1 << 16);
@@ -146,12 +148,12 @@ __global__ __launch_bounds__(kFBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
             s += c[k];
         }
         lds_barrier();
-        // scatter into sorted order: run start + rank (cnt[kWin] for no entry, never stored)
+        // scatter into sorted order: run start + rank (cnt[kWin16] for no entry, never stored)
 #pragma unroll
         for (uint32_t t0 = 0; t0 < kFPer; t0 += kFPer / 2) {
             uint32_t sb[kFPer / 2];
 #pragma unroll
-            for (uint32_t j = 0; j < kFPer / 2; j++) sb[j] = cnt[v[t0 + j] >> kS2];
+            for (uint32_t j = 0; j < kFPer / 2; j++) sb[j] = cnt[v[t0 + j] >> kS16];
 #pragma unroll
             for (uint32_t j = 0; j < kFPer / 2; j++) {
                 const uint32_t t = t0 + j;
@@ -167,11 +169,11 @@ __global__ __launch_bounds__(kFBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
 #pragma unroll
             for (uint32_t u = 0; u < 4; u++) w[u] = x0 + u * kFBlock < total ? stage[x0 + u * kFBlock] : 0u;
 #pragma unroll
-            for (uint32_t u = 0; u < 4; u++) t[u] = dlx[w[u] >> kS2];
+            for (uint32_t u = 0; u < 4; u++) t[u] = dlx[w[u] >> kS16];
             if (!over) {  // no region full in this chunk (the normal case)
 #pragma unroll
                 for (uint32_t u = 0; u < 4; u++)
-                    if (x0 + u * kFBlock < total) L[t[u] + x0 + u * kFBlock] = (uint16_t)(w[u] & (kSub - 1));
+                    if (x0 + u * kFBlock < total) L[t[u] + x0 + u * kFBlock] = (uint16_t)(w[u] & (kSub16 - 1));
             } else {
                 if (x0 == 0) *ws_flag(q) = 1;  // deg takes atomics before the histogram
 #pragma unroll
@@ -179,8 +181,8 @@ __global__ __launch_bounds__(kFBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
                     const uint32_t x = x0 + u * kFBlock;
                     if (x < total) {
                         const uint32_t slot = t[u] + x;
-                        if (slot < wend[w[u] >> kS2])
-                            L[slot] = (uint16_t)(w[u] & (kSub - 1));
+                        if (slot < wend[w[u] >> kS16])
+                            L[slot] = (uint16_t)(w[u] & (kSub16 - 1));
                         else
                             deg_atomic_add(q.deg, w[u], 1u);
                     }

@@ -379,3 +379,18 @@ def test_fused_degrees_on_wide_positions_and_misaligned_output():
     torch.cuda.synchronize()
     assert np.array_equal(_u32(view), E)
     assert np.array_equal(_u32(deg2).astype(np.uint64), oracle.count_degrees(E, n))
+
+
+@pytest.mark.parametrize("n,d,seed", [(3, 1 << 20, 4), (100, 100000, 6), (70000, 300, 2)])
+def test_stored_degrees_of_very_heavy_nodes(n, d, seed):
+    # nodes with far more than 65535 second endpoints in one histogram part:
+    # the packed 16-bit counters wrap and the block's counter sum differs
+    # from its entry count, so the part goes to deg by global atomics
+    _say("heavy stored degrees", n, d, seed)
+    edges, deg = ba.generate(n, d, seed, degrees=True)
+    torch.cuda.synchronize()
+    E, _ = oracle.bb_generate(n, d, seed)
+    assert np.array_equal(_u32(edges), E)
+    ref = oracle.count_degrees(E, n)
+    assert ref.max() > 65536
+    assert np.array_equal(_u32(deg).astype(np.uint64), ref)
