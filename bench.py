@@ -11,8 +11,14 @@ all 2^26 nodes.  Outputs and the degree workspace stay allocated across steps
 Prints one JSON line.  `value` is edges per second of the timed steps.
 Every kernel of a step is timed live with HIP events on the stream it runs
 on (the library's timing hook); `roofline` is that of the kernel with the
-largest share of the step, `kernels` gives every kernel's share and roofline
-fraction.  `cpu_baseline` times the CPU oracle (sequential Batagelj-Brandes
+largest share of the step, against its algorithmic work (ALU lane-cycles
+priced by the frozen per-instruction costs below, and 8 bytes per edge);
+`kernels` gives every kernel's share and roofline fraction, `path` the whole
+step against the method's 8.25 bytes per edge.  The other two parts of the
+metric follow: `batched_over_single` (the 4096-instance batch against the
+single-graph chain kernel, both edge pairs only) and `served_p50_ms` /
+`served_p99_ms` (the 4000-request trace through the continuous-batching
+server).  `cpu_baseline` times the CPU oracle (sequential Batagelj-Brandes
 plus the degree count) on a bounded prefix of the same graph;
 `cpu_recompute` times the oracle's per-edge recomputation on every granted
 host core (the paper's own parallel method on the CPU), edges only.
@@ -35,30 +41,36 @@ N, D, SEED = 1 << 26, 16, 7
 M = N * D
 HBM_PEAK = 8.0e12                          # MI355X HBM3E, bytes/s
 VALU_PEAK = 256 * 64 * 2.4e9               # 32-bit lane-cycles/s: 256 CUs x 64 lanes x 2.4 GHz
-# Algorithmic work per edge:
-#  chain kernel: hash evaluations per edge of this graph (2,147,478,402 over
-#  its 2^30 edges, counted by the CPU oracle) x VALU issue cycles of one
-#  narrow (r < 2^32) evaluation, plus fixed cycles per edge; it writes the
-#  8-byte edge pair and the 4-byte target of the degree pipeline;
-#  partition: reads the 4-byte target, writes a 2-byte local index;
-#  histogram: reads the 2-byte index; writes the 4-byte count of each node
-#  (a whole graph's counts start from d, so they are stored, not read back).
+# Algorithmic work, frozen: the VALU instructions of a
+# plain 32-bit lowering of the hash and of the per-edge work, priced at the
+# issue costs `bench.py --workload rates` measured on the MI355X (lane-cycles
+# at 2.4 GHz: multiplies 1.151, alignbit 1.041, add3 1.046, simple 0.634):
+#   narrow hash (r < 2^32): 11 multiplies + 3 alignbit + 2 add3 + 15 simple = 27.38
+#   wide hash (any r):      15 multiplies + 3 alignbit + 2 add3 + 20 simple = 35.15
+#   per edge besides its hash evaluations: 2 multiplies + 13 simple       = 10.54
+# Hash evaluations per edge of this graph: 2,147,478,402 over its 2^30 edges
+# (counted by the CPU oracle).  Bytes: the edge pairs (8 per edge) and the
+# degree array (4 per node); region entries of the degree pipeline (2 bytes
+# per edge, written by the fused generator and read by the histogram) are
+# the implementation's own traffic, not the method's.
+ALU_NARROW_HASH = 27.38
+ALU_WIDE_HASH = 35.15
+ALU_FIXED = 10.54
 HASH_PER_EDGE = 2147478402 / M
-CYCLES_PER_HASH = 17.0
-CYCLES_PER_EDGE = 2.0
-GEN_BYTES_PER_EDGE = 12.0
-PART_BYTES_PER_EDGE = 6.0
-HIST_BYTES = 2.0 * M + 4.0 * N
+ALU_PER_EDGE = HASH_PER_EDGE * ALU_NARROW_HASH + ALU_FIXED
+EDGE_BYTES = 8.0
+DEG_BYTES = 4.0 * N
+HIST_IMPL_BYTES = 2.0 * M + 4.0 * N
 KERNEL_NAMES = {
-    "gen": "k_gen_u32 (chain + edge pairs + target list)",
-    "part": "k_deg_part (radix partition of targets)",
-    "hist": "k_deg_hist (LDS histograms into deg)",
+    "gen": "k_gen_part (chain + edge pairs + partition of second endpoints)",
+    "hist": "k_deg_hist16 (LDS histograms into deg)",
 }
 PROFILE = os.path.join(ROOT, "profiles", "pipeline_n2e26_d16_hbm_traffic.md")
 # Files holding the pipeline's kernels and the host code that launches them:
 # the committed counter summary counts only while they are unchanged.
 KERNEL_SOURCES = [
-    os.path.join(ROOT, "paper_1602_07106_amd", "csrc", f) for f in ("ba.hip", "ba_device.h", "ba_degree.h")
+    os.path.join(ROOT, "paper_1602_07106_amd", "csrc", f)
+    for f in ("ba.hip", "ba_device.h", "ba_degree.h", "ba_genpart.h")
 ]
 
 
@@ -145,13 +157,13 @@ def copy_calibration(nbytes: int) -> int:
 
 
 def kernel_rooflines(per_launch_s: dict) -> dict:
-    """Roofline of each main kernel from its measured mean launch time."""
+    """Roofline of each main kernel of the step from its measured mean launch
+    time, against its algorithmic work (the binding bound is the longer of
+    the ALU and HBM times at peak)."""
     out = {}
     t = per_launch_s.get("gen")
     if t:
-        # both bounds of the chain kernel; the binding one is the longer
-        cyc = (HASH_PER_EDGE * CYCLES_PER_HASH + CYCLES_PER_EDGE) * M
-        nbytes = GEN_BYTES_PER_EDGE * M
+        cyc, nbytes = ALU_PER_EDGE * M, EDGE_BYTES * M
         alu, hbm = cyc / t, nbytes / t
         if nbytes / HBM_PEAK >= cyc / VALU_PEAK:
             out["gen"] = {"bound": "hbm", "achieved": hbm / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
@@ -160,12 +172,12 @@ def kernel_rooflines(per_launch_s: dict) -> dict:
             out["gen"] = {"bound": "alu", "achieved": alu / 1e12, "peak": VALU_PEAK / 1e12, "unit": "Tlane-cycles/s",
                           "frac": alu / VALU_PEAK, "hbm_frac": hbm / HBM_PEAK}
         out["gen"].update({"alg_bytes": nbytes, "alg_cycles": cyc})
-    for k, nbytes in (("part", PART_BYTES_PER_EDGE * M), ("hist", HIST_BYTES)):
-        t = per_launch_s.get(k)
-        if t:
-            bw = nbytes / t
-            out[k] = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                      "frac": bw / HBM_PEAK, "alg_bytes": nbytes}
+    t = per_launch_s.get("hist")
+    if t:
+        bw = DEG_BYTES / t
+        out["hist"] = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                       "frac": bw / HBM_PEAK, "alg_bytes": DEG_BYTES, "impl_bytes": HIST_IMPL_BYTES,
+                       "impl_frac": HIST_IMPL_BYTES / t / HBM_PEAK}
     return out
 
 
@@ -184,7 +196,7 @@ def batch_roofline(cyc: float, nbytes: float, t: float, ms_per_step: float, laun
     return r
 
 
-def bench_batch(args) -> int:
+def batch_line(args) -> dict:
     """The batched workload: 4096 independent graphs (workloads.batch_instances,
     7.64e10 edges, 611 GB of edge pairs) in HBM-budgeted rounds of 64 GiB,
     one persistent launch per round into the same round buffer.  A step is a
@@ -247,7 +259,7 @@ def bench_batch(args) -> int:
     hashes = float((m * (2.0 - 1.77 / np.sqrt(m))).sum())
     gen_ms, gen_n = kt["gen"]
     t_launch = gen_ms / 1e3 / args.steps  # kernel time of one pass (all rounds)
-    cyc = hashes * CYCLES_PER_HASH + total * CYCLES_PER_EDGE
+    cyc = hashes * ALU_NARROW_HASH + total * ALU_FIXED  # every instance's positions are below 2^32
     line = {
         "metric": "edges/s, 4096-instance batch (batched vs single)",
         "value": value,
@@ -267,11 +279,15 @@ def bench_batch(args) -> int:
         "batched_over_single": value / single_rate,
         "roofline": batch_roofline(cyc, 8.0 * total, t_launch, gen_ms / args.steps, gen_n),
     }
-    print(json.dumps(line), flush=True)
+    return line
+
+
+def bench_batch(args) -> int:
+    print(json.dumps(batch_line(args)), flush=True)
     return 0
 
 
-def bench_served(args) -> int:
+def served_line(args) -> dict:
     """The served workload: the 4000-request trace of workloads.served_trace
     (Poisson arrivals at 2000/s; half edge lists, half first-10^5 degrees)
     replayed in real time against a continuous-batching server with a
@@ -356,19 +372,19 @@ def bench_served(args) -> int:
         "served_edges_per_s": total / makespan,
         "offered_edges_per_s": total / float(arrival[-1]),
     }
-    print(json.dumps(line), flush=True)
+    return line
+
+
+def bench_served(args) -> int:
+    print(json.dumps(served_line(args)), flush=True)
     return 0
 
 
 # Streaming workload: n=2^30, d=64, seed=42, degrees of nodes 0..10^5-1 and
 # the edge checksum over all 2^36 edges (64-bit positions, nothing stored).
-# Algorithmic VALU issue cycles: 22.5 per evaluation of the general hash
-# (7 multiply-class + 3 alignbit + 2 add3 at 1, 9 xor/shift at 0.5, parity
-# test 1) at the ideal-hash mean of evaluations per edge, plus 17 per edge
-# (two 64-bit divisions by d and the checksum word's 64-bit product).
+# Algorithmic work: the frozen wide-hash price (positions reach 2^37) at the
+# ideal-hash mean of evaluations per edge, plus the per-edge price.
 STREAM = (1 << 30, 64, 42, 100000)
-STREAM_CYCLES_PER_HASH = 22.5
-STREAM_CYCLES_PER_EDGE = 17.0
 
 
 def bench_stream(args) -> int:
@@ -397,7 +413,7 @@ def bench_stream(args) -> int:
     st_ms, st_n = kt["stream"]
     t = st_ms / st_n / 1e3
     hashes = m * (2.0 - 1.77 / m ** 0.5)
-    cyc = hashes * STREAM_CYCLES_PER_HASH + m * STREAM_CYCLES_PER_EDGE
+    cyc = hashes * ALU_WIDE_HASH + m * ALU_FIXED
     line = {
         "metric": "edges/s, streamed first-10^5 degrees at n=2^30, d=64",
         "value": m / (ms / 1e3),
@@ -481,7 +497,7 @@ def bench_model(args) -> int:
     main = variants["fmix"]
     t = main["kernel_ms"] / 1e3
     hashes = m * (2.0 - 1.77 / m ** 0.5)
-    cyc = hashes * CYCLES_PER_HASH + m * CYCLES_PER_EDGE
+    cyc = hashes * ALU_NARROW_HASH + m * ALU_FIXED
     byts = 8.0 * m
     line = {
         "metric": "edges/s, generalized model (100-node, 1000-edge seed graph) at n=2^26, d=16",
@@ -518,17 +534,76 @@ def bench_model(args) -> int:
     return 0
 
 
+# Issue-rate microbenchmark (libba_rates.so): lane-cycles one VALU
+# instruction of each kind costs at 2.4 GHz when every lane runs 8
+# independent chains of it (8 waves per SIMD), and the 16-byte fill rate.
+RATE_OPS = ("mul_lo_u32", "mul_hi_u32", "mad_u64_u32", "alignbit_b32", "add3_u32", "xor_b32", "lshrrev_b32",
+            "add_u32")
+
+
+def bench_rates(args) -> int:
+    import ctypes
+
+    import torch
+
+    from paper_1602_07106_amd import build as _b
+
+    L = ctypes.CDLL(_b.RATES_LIB)
+    L.ba_rate_run.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                              ctypes.POINTER(ctypes.c_float)]
+    L.ba_rate_fill.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p,
+                               ctypes.POINTER(ctypes.c_float)]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    blocks, iters = cus * 8, 4096
+    sink = torch.zeros(blocks, dtype=torch.int32, device=dev)
+    st = torch.cuda.current_stream().cuda_stream
+    lane_cycles_per_s = VALU_PEAK  # 256 CUs x 64 lanes x 2.4 GHz
+    ops = {}
+    for k, name in enumerate(RATE_OPS):
+        best = None
+        for _ in range(max(2, args.steps // 4)):
+            ms = ctypes.c_float(0)
+            rc = L.ba_rate_run(k, blocks, iters, sink.data_ptr(), st, ctypes.byref(ms))
+            if rc:
+                raise RuntimeError("ba_rate_run(%s) failed: %d" % (name, rc))
+            best = ms.value if best is None else min(best, ms.value)
+        n_ops = blocks * 256 * iters * L.ba_rate_ops_per_iter(k)
+        rate = n_ops / (best / 1e3)
+        ops[name] = {"lane_ops_per_s": rate, "lane_cycles_per_op": round(lane_cycles_per_s / rate, 3),
+                     "ms": round(best, 3)}
+    nbytes = 4 << 30
+    buf = torch.empty(nbytes // 4, dtype=torch.int32, device=dev)
+    fill = None
+    for _ in range(max(3, args.steps // 4)):
+        ms = ctypes.c_float(0)
+        rc = L.ba_rate_fill(buf.data_ptr(), nbytes // 16, cus * 8, st, ctypes.byref(ms))
+        if rc:
+            raise RuntimeError("ba_rate_fill failed: %d" % rc)
+        fill = ms.value if fill is None else min(fill, ms.value)
+    line = {"metric": "VALU issue cost and 16-byte fill rate", "unit": "lane-cycles per instruction at 2.4 GHz",
+            "cus": cus, "blocks": blocks, "threads_per_block": 256, "chains_per_lane": 8, "iters": iters,
+            "ops": ops, "fill_bytes": nbytes, "fill_ms": round(fill, 4),
+            "fill_GB_per_s": round(nbytes / (fill / 1e3) / 1e9, 1)}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["graph", "batch", "served", "stream", "model"], default="graph",
+    ap.add_argument("--workload", choices=["graph", "batch", "served", "stream", "model", "rates"], default="graph",
                     help="graph: the n=2^26, d=16 graph with degrees (default); batch: 4096 graphs; "
                          "served: a 4000-request trace through the continuous-batching server; "
                          "stream: streamed first-10^5 degrees at n=2^30, d=64; "
-                         "model: the generalized model (seed graph, no-self-loop draws, CRC hash)")
+                         "model: the generalized model (seed graph, no-self-loop draws, CRC hash); "
+                         "rates: VALU issue-rate and 16-byte fill microbenchmarks (the ALU roofline's prices)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="graph workload only: skip the batched and served parts of the metric")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers (reference for HBM counters)")
     args = ap.parse_args()
@@ -547,6 +622,8 @@ def main() -> int:
         return bench_model(args)
     if args.workload == "stream":
         return bench_stream(args)
+    if args.workload == "rates":
+        return bench_rates(args)
 
     import torch
 
@@ -594,9 +671,10 @@ def main() -> int:
         e = {"ms_per_launch": round(ms / n, 4), "launches": n, "share_of_step": round(ms / gpu_ms, 4)}
         if k in roofs:
             e.update({"bound": roofs[k]["bound"], "frac": round(roofs[k]["frac"], 4)})
-            for f in ("hbm_frac", "alu_frac"):
+            for f in ("hbm_frac", "alu_frac", "impl_frac"):
                 if f in roofs[k]:
                     e[f] = round(roofs[k][f], 4)
+            e["traffic"] = traffic.get(k)
         kernels[k] = e
     dom = max(roofs, key=lambda k: kt[k][0])
     r = roofs[dom]
@@ -610,11 +688,12 @@ def main() -> int:
             if f in r:
                 roof[f] = round(r[f], 4)
     # the whole step against the method's own bytes (edge pairs + degree
-    # array: 8 B per edge + 4 B per node) and its hash work
+    # array: 8 B per edge + 4 B per node) and its frozen ALU work
     step_s = ms_per_step / 1e3
-    path = {"alg_bytes_per_edge": (8.0 * M + 4.0 * N) / M,
-            "hbm_frac": round((8.0 * M + 4.0 * N) / step_s / HBM_PEAK, 4),
-            "alu_frac": round((HASH_PER_EDGE * CYCLES_PER_HASH + CYCLES_PER_EDGE) * M / step_s / VALU_PEAK, 4)}
+    path = {"alg_bytes_per_edge": (EDGE_BYTES * M + DEG_BYTES) / M,
+            "hbm_frac": round((EDGE_BYTES * M + DEG_BYTES) / step_s / HBM_PEAK, 4),
+            "alg_lane_cycles_per_edge": round(ALU_PER_EDGE, 2),
+            "alu_frac": round(ALU_PER_EDGE * M / step_s / VALU_PEAK, 4)}
 
     line = {
         "metric": "edges/s at n=2^26,d=16 (bit-exact)",
@@ -636,6 +715,24 @@ def main() -> int:
         "path": path,
         "wall_s": round(wall, 3),
     }
+    if not args.no_extras:
+        # the other two parts of the metric: batched vs single-graph edges/s
+        # (4096-instance table, 3 timed passes) and the served trace's p50/p99
+        del out, deg, ws
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        b = batch_line(argparse.Namespace(steps=3, warmup=1))
+        line["batched_edges_per_s"] = b["value"]
+        line["single_graph_edges_per_s"] = b["single_graph_edges_per_s"]
+        line["batched_over_single"] = b["batched_over_single"]
+        line["batch_roofline"] = b["roofline"]
+        torch.cuda.empty_cache()
+        sv = served_line(args)
+        line["served_p50_ms"] = sv["p50_ms"]
+        line["served_p99_ms"] = sv["p99_ms"]
+        line["served_edges_per_s"] = sv["served_edges_per_s"]
+        line["served_trace"] = {"requests": sv["config"]["requests"], "arrival_span_s": sv["arrival_span_s"],
+                                "makespan_s": sv["makespan_s"], "offered_edges_per_s": sv["offered_edges_per_s"]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
         line["cpu_recompute"] = cpu_recompute_threads()

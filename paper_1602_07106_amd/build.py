@@ -14,6 +14,9 @@ ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "ba.hip")
 DEPS = [SRC, os.path.join(ROOT, "include", "ba.h")] + sorted(glob.glob(os.path.join(PKG, "csrc", "*.h")))
 LIB = os.path.join(PKG, "libba.so")
+# issue-rate and store-rate microbenchmarks that price the ALU roofline (bench.py --workload rates)
+RATES_SRC = os.path.join(PKG, "csrc", "ba_rates.hip")
+RATES_LIB = os.path.join(PKG, "libba_rates.so")
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -33,17 +36,23 @@ def hipcc() -> str:
     return os.path.join(rocm, "bin", "hipcc")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile libba.so; always recompiles (the build check must compile)."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-o", tmp, SRC]
+def _compile(src: str, lib: str, verbose: bool) -> None:
+    tmp = lib + ".tmp%d" % os.getpid()
+    cmd = [hipcc()] + HIPCC_FLAGS + ["-o", tmp, src]
     res = subprocess.run(cmd, capture_output=True, text=True)
     msgs = [ln for ln in (res.stdout + res.stderr).splitlines() if "packed-fp32-ops" not in ln]
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + "\n".join(msgs))
     if verbose and msgs:
         print("\n".join(msgs), file=sys.stderr)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libba.so and libba_rates.so; always recompiles (the build check
+    must compile)."""
+    _compile(SRC, LIB, verbose)
+    _compile(RATES_SRC, RATES_LIB, verbose)
     return LIB
 
 
