@@ -1,7 +1,8 @@
 """GPU parity of batched generation (many graphs in one persistent launch)
 against the CPU oracle, bit-exact: ragged tables, every kernel shape,
 misaligned outputs, a wide instance, the full 4096-instance workload in
-rounds (sampled per instance), and replays of a captured HIP graph."""
+rounds as bench.py runs it (every instance sampled, 256 of them, the 16
+largest among them, compared whole), and replays of a captured HIP graph."""
 import random
 import sys
 
@@ -10,6 +11,7 @@ import pytest
 
 import oracle
 import workloads
+from tests import oracle_par
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -118,19 +120,37 @@ def test_batch_with_a_wide_instance():
         assert np.array_equal(got, ref.astype(np.uint32).reshape(-1))
 
 
-def test_full_batched_workload_in_rounds_sampled():
+def test_full_batched_workload_in_rounds():
     n, d, s = workloads.batch_instances()
     round_elems = 1 << 34  # 64 GiB of uint32 per round
     r, off, rounds = ba.batch_plan_rounds(n, d, round_elems)
     assert rounds >= 8
     out = torch.empty(round_elems, dtype=torch.int32, device="cuda")
     rng = np.random.default_rng(5)
+    # compared whole: the 16 largest instances and 240 others
+    m_all = n.astype(np.int64) * d.astype(np.int64)
+    largest = np.argsort(-m_all)[:16]
+    rest = np.setdiff1d(np.arange(n.size), largest)
+    whole = set(largest.tolist()) | set(np.random.default_rng(17).choice(rest, 240, replace=False).tolist())
+    assert len(whole) == 256
+    compared = 0
     total = 0
     for k in range(rounds):
         js = np.flatnonzero(r == k)
         _say("round", k, "instances", len(js))
         b = ba.Batch(n[js], d[js], s[js], out_offset=off[js])
+        if k == 0:
+            b.autotune(out)  # as bench.py: the tuned shape for every round
         b.launch(out)
+        for j in js:
+            if int(j) in whole:
+                m = int(m_all[j])
+                got = out[int(off[j]):int(off[j]) + 2 * m].cpu().numpy().view(np.uint32)
+                ref = oracle_par.edges_u32(int(d[j]), int(s[j]), 0, m)
+                if not np.array_equal(got, ref):
+                    x = int(np.flatnonzero(got != ref)[0])
+                    pytest.fail("instance %d (n=%d d=%d) differs first at element %d" % (j, n[j], d[j], x))
+                compared += 1
         # samples: first 32, last 32 and 64 random edges of every instance
         idx, refs = [], []
         for j in js:
@@ -148,6 +168,7 @@ def test_full_batched_workload_in_rounds_sampled():
         got = out[sel].cpu().numpy().view(np.uint32)
         assert np.array_equal(got, np.concatenate(refs)), "round %d" % k
     assert total == int((n.astype(np.float64) * d).sum())
+    assert compared == 256
 
 
 def test_batch_launch_replays_from_a_captured_graph():

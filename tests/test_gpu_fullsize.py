@@ -3,12 +3,13 @@ configuration bench.py times.
 
 * Stored graph n=2^26, d=16, seed=7 (2^30 edges): every edge and every degree
   against the sequential Batagelj-Brandes oracle (about 30 s of CPU), bit-exact.
-* Streamed degrees n=2^30, d=64, seed=42 (2^36 edges, 64-bit positions): the
-  oracle cannot run 2^36 edges, so the full run is checked by (a) its first
-  2^28 edges and its last 2^20 edges (positions near 2^37) against the oracle's
-  stream over the same edges, bit-exact, (b) invariance under splitting the
-  edges into shuffled ranges, and (c) properties that hold at any size:
-  the mean-field degree law E[deg v] ~ d*sqrt(n/v) and deg >= d.
+* Streamed degrees n=2^30, d=64, seed=42 (2^36 edges, 64-bit positions): (a)
+  the degrees of the first 10^5 nodes and the checksum over all 2^36 edges
+  against the oracle's per-edge recomputation over the same edges, run on
+  every granted host core in disjoint ranges (about a minute), bit-exact;
+  (b) invariance under splitting the edges into shuffled ranges; (c) the
+  mean-field degree law E[deg v] ~ d*sqrt(n/v) and deg >= d.
+* The same streaming workload at the reduced n=2^24 (2^30 edges), whole.
 """
 import random
 import sys
@@ -17,6 +18,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests import oracle_par
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -87,16 +89,11 @@ def test_streaming_workload_full_size():
     assert np.array_equal(acc.cpu().numpy().view(np.uint64), full)
     assert int(acc_cs.item()) & ((1 << 64) - 1) == cs
 
-    # (a) prefix and suffix against the oracle's stream over the same edges
-    for b, c in [(0, 1 << 28), (m - (1 << 20), 1 << 20)]:
-        _say("oracle stream", b, c)
-        g = torch.zeros(k, dtype=torch.int64, device="cuda")
-        gcs = torch.zeros(1, dtype=torch.int64, device="cuda")
-        ba.degrees_range(n, d, seed, b, c, k, g, gcs)
-        torch.cuda.synchronize()
-        rdeg, rcs, _ = oracle.stream(d, seed, b, c, k)
-        assert np.array_equal(g.cpu().numpy().view(np.uint64), rdeg)
-        assert int(gcs.item()) & ((1 << 64) - 1) == rcs
+    # (a) every edge: the oracle's stream over all 2^36 edges, on all granted host cores
+    _say("oracle stream over all", m, "edges on", oracle_par.THREADS, "threads")
+    rdeg, rcs = oracle_par.stream(d, seed, 0, m, k)
+    assert np.array_equal(full, rdeg)
+    assert cs == rcs
 
     # (c) properties at full size: every node has its d own edges, and the
     # mean-field BA law E[deg v] = d sqrt(n/v) holds on average over v
@@ -104,3 +101,17 @@ def test_streaming_workload_full_size():
     v = np.arange(1000, k)
     ratio = full[1000:].astype(np.float64) / (d * np.sqrt(n / v))
     assert abs(ratio.mean() - 1.0) < 0.05
+
+
+def test_streaming_workload_reduced_n_whole():
+    # the streaming workload at n = 2^24 (same d and seed): 2^30 edges, all
+    # compared, on the LDS tier the automatic choice takes (64K) and the other
+    n, d, seed, k = 1 << 24, 64, 42, 100000
+    m = n * d
+    _say("streamed degrees, reduced n", n, d, seed, k)
+    rdeg, rcs = oracle_par.stream(d, seed, 0, m, k)
+    for tier in (ba.TIER_AUTO, ba.TIER_16K):
+        deg, cs = ba.degrees(n, d, seed, k, tier=tier)
+        torch.cuda.synchronize()
+        assert np.array_equal(deg.cpu().numpy().view(np.uint64), rdeg), tier
+        assert cs == rcs, tier

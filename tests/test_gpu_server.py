@@ -1,7 +1,9 @@
 """GPU parity of served generation (continuous batching): every result of a
 mixed request stream equals the CPU oracle's for that request alone,
 bit-exact, under an arena small enough to force many steps, admission waits
-and out-of-arena failures."""
+and out-of-arena failures; and a slice of the real served trace at full
+size (an n=2^27 edge list, first-10^5 degrees on both LDS tiers, 64-bit
+positions in edge and degree requests), every result compared whole."""
 import sys
 
 import numpy as np
@@ -9,6 +11,7 @@ import pytest
 
 import oracle
 import workloads
+from tests import oracle_par
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -108,4 +111,56 @@ def test_server_validation():
     while srv.poll(t)[0] != ba.JOB_READY:
         srv.pump()
     srv.release(t)
+    srv.close()
+
+
+def test_served_trace_slice_at_full_size():
+    tr = workloads.served_trace()
+    n = tr["n"].astype(np.int64)
+    d = tr["d"].astype(np.int64)
+    m = n * d
+    kind, k = tr["kind"], tr["first_k"].astype(np.int64)
+
+    def first(mask):
+        return int(np.flatnonzero(mask)[0])
+
+    picks = {
+        "n=2^27 edges": first((n == 1 << 27) & (kind == 0)),
+        "n=2^27 degrees (16K tier)": first((n == 1 << 27) & (kind == 1)),
+        "degrees, 64-bit positions": first((kind == 1) & (2 * m > 1 << 32) & (m <= 4e9) & (n != 1 << 27)),
+        "degrees, 64K tier": first((kind == 1) & (k == 100000) & (n < 5e7) & (n > 2e5)),
+        "degrees, first_k = n": first((kind == 1) & (n < 100000)),
+        "edges, 64-bit positions": first((kind == 0) & (2 * m > 1 << 32) & (m <= 3e9) & (n != 1 << 27)),
+    }
+    sel = sorted(set(picks.values()) | set([j for j in range(60) if m[j] <= 1e9][:40]))
+    srv = ba.Server(48 << 30)
+    ticket_of = {}
+    for j in sel:  # arrival order
+        if kind[j] == 0:
+            t = srv.submit_edges(int(n[j]), int(d[j]), int(tr["seed"][j]))
+        else:
+            t = srv.submit_degrees(int(n[j]), int(d[j]), int(tr["seed"][j]), int(k[j]))
+        ticket_of[t] = j
+    _say("served slice", len(sel), "requests", {name: int(j) for name, j in picks.items()})
+    done = 0
+    while done < len(sel):
+        srv.pump(max_inflight=2)
+        for t in srv.completed():
+            j = ticket_of[t]
+            st, _, _, _ = srv.poll(t)
+            assert st == ba.JOB_READY, "request %d failed" % j
+            res = srv.result(t)
+            dj, sj = int(d[j]), int(tr["seed"][j])
+            if kind[j] == 0:
+                got = res.view(torch.int32).cpu().numpy().view(np.uint32)
+                ref = oracle_par.edges_u32(dj, sj, 0, int(m[j]))
+                assert np.array_equal(got, ref), "edges request %d (n=%d d=%d)" % (j, n[j], dj)
+            else:
+                got = res.view(torch.int64).cpu().numpy().view(np.uint64)
+                kj = int(k[j])
+                rdeg, rcs = oracle_par.stream(dj, sj, 0, int(m[j]), kj)
+                assert np.array_equal(got[:kj], rdeg) and int(got[kj]) == rcs, "degrees request %d" % j
+            srv.release(t)
+            done += 1
+    assert srv.stats() == (0, 0, 0)
     srv.close()
