@@ -309,7 +309,10 @@ def served_line(args) -> dict:
     ts = [w.submit_edges(5000, 4, 1), w.submit_edges(1 << 22, 2, 1), w.submit_degrees(5000, 4, 1, 100),
           w.submit_degrees(1 << 31, 2, 1, 100)]
     left = set(ts)
+    t_end = time.perf_counter() + 60
     while left:
+        if time.perf_counter() > t_end:
+            raise RuntimeError("served warm-up made no progress in 60 s")
         w.pump()
         for t in w.completed():
             w.release(t)
@@ -327,6 +330,8 @@ def served_line(args) -> dict:
     i = done = 0
     while done < count:
         now = time.perf_counter() - t0
+        if now > arrival[-1] + 120:
+            raise RuntimeError("served trace not finished 120 s after its last arrival (%d of %d done)" % (done, count))
         while i < count and arrival[i] <= now:
             if tr["kind"][i] == 0:
                 t = srv.submit_edges(int(tr["n"][i]), int(tr["d"][i]), int(tr["seed"][i]))

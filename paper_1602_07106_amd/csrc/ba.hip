@@ -1251,7 +1251,7 @@ int ba_server_create(void *arena, uint64_t arena_bytes, void *stream, ba_server 
     s->arena_bytes = arena_bytes & ~(uint64_t)255;
     s->stream = (hipStream_t)stream;
     s->alloc = ArenaAlloc(s->arena_bytes);
-    s->slot_bytes = batch_layout(kServerMaxBatch).bytes;
+    s->slot_bytes = batch_layout(kServerMaxBatch).bytes + stream_table_bytes(kServerMaxDeg);
     int rc = hip_check(hipHostMalloc((void **)&s->staging, s->slot_bytes * kServerSlots, hipHostMallocDefault));
     if (!rc) rc = hip_check(hipEventCreate(&s->start));
     if (!rc) rc = hip_check(hipEventRecord(s->start, s->stream));

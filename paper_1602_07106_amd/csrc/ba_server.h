@@ -2,13 +2,16 @@
 //
 // Requests (a whole edge list, or the first-k degrees and checksum of a
 // graph) queue on the host.  Each pump admits queued requests in arrival
-// order while their outputs fit the caller's device arena (admission by
-// HBM bytes), launches all admitted edge-list requests as ONE batched
-// persistent launch (the instance table goes to the arena from pinned
-// staging) and every admitted degree request as a streaming launch, and
-// records one event for the step.  Steps queue on the server's stream, so
-// the host admits the next batch while earlier ones run; results stay in
-// the arena (device-resident) until the client releases them.
+// order whose outputs fit the caller's device arena (admission by HBM
+// bytes); a request that does not fit is passed over, not waited for, until
+// it has been passed over kServerMaxBypass steps in a row, after which
+// nothing behind it is admitted until it fits.  All admitted edge-list
+// requests run as ONE batched persistent launch, all admitted degree
+// requests as one batched streaming launch per LDS tier (their tables go to
+// the arena from pinned staging), and the step records one event.  Steps
+// queue on the server's stream, so the host admits the next batch while
+// earlier ones run; results stay in the arena (device-resident) until the
+// client releases them.
 //
 // The paper hands batches of edge IDs to processors as they become free
 // (Section 2, last paragraph); here whole requests are the units and the
@@ -81,13 +84,27 @@ struct ServerJob {
 
 struct ServerStep {
     hipEvent_t ev = nullptr;
-    uint64_t table_off = 0, table_bytes = 0;
-    int slot = -1;  // pinned staging slot holding the table, returned when the step retires
+    uint64_t table_off = 0, table_bytes = 0;  // the step's tables in the arena (edge batch, then degree requests)
+    int slot = -1;  // pinned staging slot holding the tables, returned when the step retires
+    ba_batch_info info{};         // the edge batch
+    uint64_t units[2] = {0, 0};   // units of the batched streaming launches (16K, 64K tier)
     std::vector<uint64_t> jobs;
 };
 
 constexpr uint32_t kServerSlots = 8;         // steps in flight at most
 constexpr uint32_t kServerMaxBatch = 4096;   // edge requests per step at most
+constexpr uint32_t kServerMaxDeg = kStreamBatchJobs;  // degree requests per step at most
+constexpr uint32_t kServerLookahead = 1024;  // queued requests one pump examines
+constexpr uint32_t kServerMaxBypass = 8;     // steps a head request may be passed over
+// degree requests with more edges than this run as single streaming launches
+constexpr uint64_t kServerBatchedEdges = 1ull << 40;
+
+// The degree requests' table of a step: StreamJob entries (16K-tier
+// requests, then 64K-tier ones) and the two tiers' unit counters.
+static inline uint64_t stream_table_bytes(uint32_t njobs)
+{
+    return align256(sizeof(StreamJob) * (uint64_t)njobs + 2 * sizeof(uint32_t));
+}
 
 }  // namespace ba
 
@@ -108,6 +125,7 @@ struct ba_server {
     unsigned char *staging = nullptr;  // kServerSlots pinned table slots
     uint64_t slot_bytes = 0;
     std::vector<int> free_slots;
+    uint32_t head_passed = 0;  // steps in a row that admitted requests behind a head that did not fit
 };
 
 namespace ba {
@@ -159,33 +177,114 @@ static int server_retire(ba_server *s)
     return BA_OK;
 }
 
-// One step: admit queued jobs in order while they fit, launch them.
+// Fills the StreamJob of a degree request for a batched streaming launch of
+// `grid` blocks on the given tier; returns its units.
+static uint64_t stream_job(const ServerJob &J, bool packed, uint32_t grid, StreamJob *out)
+{
+    StreamJob &S = *out;
+    S = StreamJob{};
+    S.key = make_hash_key(J.req.seed);
+    S.narrow = 2 * J.m <= ((uint64_t)1 << 32) ? 1u : 0u;
+    S.div = make_divider(J.req.d ? J.req.d : 1u);
+    S.m = J.m;
+    S.k = J.req.first_k;
+    S.out = J.out_off / 8;  // uint64 elements from the arena base
+    // runs sized so the request's units spread over the grid once
+    uint64_t pw = (J.m + (uint64_t)kStreamWaves * grid - 1) / ((uint64_t)kStreamWaves * grid);
+    if (packed) {
+        pw = (pw + kStreamRoundClaims - 1) / kStreamRoundClaims * kStreamRoundClaims;
+        pw = std::min<uint64_t>(std::max<uint64_t>(pw, kStreamRoundClaims), (uint64_t)kStreamRoundClaims << 16);
+        S.rounds = pw / kStreamRoundClaims;  // no wave takes more barriers in its run
+    } else {
+        pw = (pw + kWave - 1) / kWave * kWave;
+        // a block's 32-bit LDS counts of one unit stay below 16 * 2^26 = 2^30
+        pw = std::min<uint64_t>(std::max<uint64_t>(pw, 4 * kWave), (uint64_t)1 << 26);
+    }
+    S.per_wave = pw;
+    return J.m ? (J.m + (uint64_t)kStreamWaves * pw - 1) / ((uint64_t)kStreamWaves * pw) : 0;
+}
+
+// One step: admit queued jobs that fit (in arrival order, passing over
+// those that do not), launch them.
 static int server_launch_step(ba_server *s, uint32_t *launched)
 {
     std::vector<uint64_t> edge_jobs, deg_jobs;
     *launched = 0;
-    if (s->free_slots.empty()) return BA_OK;  // every staging slot is in flight
-    while (!s->queue.empty()) {
-        ServerJob &J = *server_job(s, s->queue.front());
-        if (J.req.kind == BA_REQ_EDGES && edge_jobs.size() == kServerMaxBatch) break;
-        uint64_t off;
-        if (!s->alloc.alloc(J.out_bytes, &off)) break;
-        J.out_off = off;
-        (J.req.kind == BA_REQ_EDGES ? edge_jobs : deg_jobs).push_back(s->queue.front());
-        s->queue.pop_front();
-    }
-    if (edge_jobs.empty() && deg_jobs.empty()) {
-        *launched = 0;
-        // a head job that can never fit an empty arena fails instead of blocking the queue
-        if (!s->queue.empty() && s->inflight == 0 && s->alloc.used() == 0) {
+    if (s->free_slots.empty() || s->queue.empty()) return BA_OK;  // every staging slot is in flight
+    // room for the step's tables first, sized for what the examined requests
+    // could need, so admitted outputs never leave the tables without room
+    const size_t look = std::min<size_t>(s->queue.size(), kServerLookahead);
+    uint32_t ce = 0, cd = 0;
+    for (size_t q = 0; q < look; q++) (server_job(s, s->queue[q])->req.kind == BA_REQ_EDGES ? ce : cd)++;
+    ce = std::min(ce, kServerMaxBatch);
+    cd = std::min(cd, kServerMaxDeg);
+    const uint64_t table_max = (ce ? batch_layout(ce).bytes : 0) + (cd ? stream_table_bytes(cd) : 0);
+    ServerStep st;
+    // a head job that can never fit the arena beside its step's table fails
+    // instead of blocking the queue
+    auto fail_head_if_stuck = [&]() {
+        if (s->inflight == 0 && s->alloc.used() == align256(st.table_bytes)) {
             server_job(s, s->queue.front())->state = BA_JOB_FAILED;
             s->completed.push_back(s->queue.front());
             s->queue.pop_front();
+            s->head_passed = 0;
         }
+    };
+    if (!s->alloc.alloc(table_max, &st.table_off)) {
+        fail_head_if_stuck();
         return BA_OK;
     }
-    ServerStep st;
+    st.table_bytes = table_max;
+    bool head_fits = true;
+    std::vector<size_t> taken;  // queue positions admitted
+    for (size_t q = 0; q < look; q++) {
+        if (!head_fits && s->head_passed >= kServerMaxBypass) break;  // the head waits for room first
+        ServerJob &J = *server_job(s, s->queue[q]);
+        auto &list = J.req.kind == BA_REQ_EDGES ? edge_jobs : deg_jobs;
+        if (list.size() == (J.req.kind == BA_REQ_EDGES ? kServerMaxBatch : kServerMaxDeg)) continue;
+        uint64_t off;
+        if (!s->alloc.alloc(J.out_bytes, &off)) {
+            if (q == 0) head_fits = false;
+            continue;
+        }
+        J.out_off = off;
+        list.push_back(s->queue[q]);
+        taken.push_back(q);
+    }
+    if (edge_jobs.empty() && deg_jobs.empty()) {
+        fail_head_if_stuck();
+        s->alloc.release(st.table_off, st.table_bytes);
+        return BA_OK;
+    }
+    // the admitted requests leave the queue
+    {
+        std::deque<uint64_t> rest;
+        size_t t = 0;
+        for (size_t q = 0; q < s->queue.size(); q++) {
+            if (t < taken.size() && taken[t] == q) t++;
+            else rest.push_back(s->queue[q]);
+        }
+        s->queue.swap(rest);
+    }
+    s->head_passed = head_fits ? 0 : s->head_passed + 1;
+    // the degree requests: batched per LDS tier, the largest ones alone
+    std::vector<uint64_t> deg16, deg64, deg_single;
+    for (uint64_t j : deg_jobs) {
+        const ServerJob &J = *server_job(s, j);
+        if (J.m > kServerBatchedEdges) {
+            deg_single.push_back(j);
+            continue;
+        }
+        const bool narrow = 2 * J.m <= ((uint64_t)1 << 32);
+        (stream_tier(J.req.n, J.req.first_k, narrow, BA_TIER_AUTO) == BA_TIER_64K ? deg64 : deg16).push_back(j);
+    }
+    const uint32_t ne = (uint32_t)edge_jobs.size(), nd = (uint32_t)(deg16.size() + deg64.size());
+    uint32_t g16 = 0, g64 = 0;
     int rc = BA_OK;
+    if (!deg16.empty() && (rc = persistent_grid(k_stream_batch<false>, kStreamBlock, &g16))) return rc;
+    if (!deg64.empty() && (rc = persistent_grid(k_stream_batch<true>, kStreamBlock, &g64))) return rc;
+    const BatchLayout L = batch_layout(ne);
+    const uint64_t eb_bytes = ne ? L.bytes : 0, sb_bytes = nd ? stream_table_bytes(nd) : 0;
     // A launch of the step failed: part of it may already be queued, so wait
     // for the stream, then fail the step's requests and free what they held.
     auto fail_step = [&](int err) {
@@ -204,56 +303,91 @@ static int server_launch_step(ba_server *s, uint32_t *launched)
         *launched = 0;
         return err;
     };
-    const uint32_t ne = (uint32_t)edge_jobs.size();
-    if (ne) {
-        const BatchLayout L = batch_layout(ne);
-        if (!s->alloc.alloc(L.bytes, &st.table_off)) {
-            // no room for the table: give the outputs back and retry next pump
-            for (auto it = deg_jobs.rbegin(); it != deg_jobs.rend(); ++it) {
-                s->alloc.release(server_job(s, *it)->out_off, server_job(s, *it)->out_bytes);
-                s->queue.push_front(*it);
-            }
-            for (auto it = edge_jobs.rbegin(); it != edge_jobs.rend(); ++it) {
-                s->alloc.release(server_job(s, *it)->out_off, server_job(s, *it)->out_bytes);
-                s->queue.push_front(*it);
-            }
-            *launched = 0;
-            return BA_OK;
-        }
-        st.table_bytes = L.bytes;
+    if (eb_bytes + sb_bytes) {
         st.slot = s->free_slots.back();
         s->free_slots.pop_back();
         unsigned char *stage = s->staging + (uint64_t)st.slot * s->slot_bytes;
-        memset(stage, 0, L.bytes);
-        BatchInst *I = (BatchInst *)(stage + L.o_inst);
-        uint64_t *T[3];
-        for (int t = 0; t < 3; t++) T[t] = (uint64_t *)(stage + L.o_tile0[t]);
-        uint64_t tiles[3] = {0, 0, 0};
-        for (uint32_t q = 0; q < ne; q++) {
-            const ServerJob &J = *server_job(s, edge_jobs[q]);
-            I[q].key = make_hash_key(J.req.seed);
-            I[q].narrow = 2 * J.m <= ((uint64_t)1 << 32) ? 1u : 0u;
-            I[q].div = make_divider(J.req.d ? J.req.d : 1u);
-            I[q].m = J.m;
-            I[q].out = J.out_off / 4;  // uint32 elements from the arena base
-            for (int t = 0; t < 3; t++) {
-                T[t][q] = tiles[t];
-                tiles[t] += (J.m + kBatchTiles[t] - 1) / kBatchTiles[t];
+        memset(stage, 0, eb_bytes + sb_bytes);
+        if (ne) {
+            BatchInst *I = (BatchInst *)(stage + L.o_inst);
+            uint64_t *T[3];
+            for (int t = 0; t < 3; t++) T[t] = (uint64_t *)(stage + L.o_tile0[t]);
+            uint64_t tiles[3] = {0, 0, 0};
+            for (uint32_t q = 0; q < ne; q++) {
+                const ServerJob &J = *server_job(s, edge_jobs[q]);
+                I[q].key = make_hash_key(J.req.seed);
+                I[q].narrow = 2 * J.m <= ((uint64_t)1 << 32) ? 1u : 0u;
+                I[q].div = make_divider(J.req.d ? J.req.d : 1u);
+                I[q].m = J.m;
+                I[q].out = J.out_off / 4;  // uint32 elements from the arena base
+                for (int t = 0; t < 3; t++) {
+                    T[t][q] = tiles[t];
+                    tiles[t] += (J.m + kBatchTiles[t] - 1) / kBatchTiles[t];
+                }
+            }
+            for (int t = 0; t < 3; t++) T[t][ne] = tiles[t];
+            st.info.count = ne;
+            for (int t = 0; t < 3; t++) st.info.tiles[t] = tiles[t];
+            st.info.edges_len = s->arena_bytes / 4;
+        }
+        if (nd) {
+            // per tier: requests with the longest runs first (their units are taken first)
+            StreamJob *SJ = (StreamJob *)(stage + eb_bytes);
+            uint32_t at = 0;
+            for (int tier = 0; tier < 2; tier++) {
+                const auto &list = tier ? deg64 : deg16;
+                const uint32_t first = at;
+                for (uint64_t j : list) (void)stream_job(*server_job(s, j), tier == 1, tier ? g64 : g16, &SJ[at++]);
+                std::stable_sort(SJ + first, SJ + at,
+                                 [](const StreamJob &x, const StreamJob &y) { return x.per_wave > y.per_wave; });
+                uint64_t units = 0;
+                for (uint32_t q = first; q < at; q++) {
+                    SJ[q].unit0 = units;
+                    units += (SJ[q].m + (uint64_t)kStreamWaves * SJ[q].per_wave - 1) /
+                             ((uint64_t)kStreamWaves * SJ[q].per_wave);
+                }
+                st.units[tier] = units;
             }
         }
-        for (int t = 0; t < 3; t++) T[t][ne] = tiles[t];
-        if ((rc = hip_check(hipMemcpyAsync(s->arena + st.table_off, stage, L.bytes, hipMemcpyHostToDevice,
-                                           s->stream))))
-            return fail_step(rc);
-        ba_batch_info info{};
-        info.count = ne;
-        for (int t = 0; t < 3; t++) info.tiles[t] = tiles[t];
-        info.edges_len = s->arena_bytes / 4;
-        if ((rc = ba_batch_launch(&info, s->arena + st.table_off, (uint32_t *)s->arena, s->arena_bytes / 4,
+        int rc2 = hip_check(hipMemcpyAsync(s->arena + st.table_off, stage, eb_bytes + sb_bytes, hipMemcpyHostToDevice,
+                                           s->stream));
+        if (rc2) return fail_step(rc2);
+    }
+    if (ne) {
+        if ((rc = ba_batch_launch(&st.info, s->arena + st.table_off, (uint32_t *)s->arena, s->arena_bytes / 4,
                                   s->stream)))
             return fail_step(rc);
     }
-    for (uint64_t j : deg_jobs) {
+    if (nd) {
+        StreamBatchArgs a{};
+        const StreamJob *SJ = (const StreamJob *)(s->arena + st.table_off + eb_bytes);
+        uint32_t *next = (uint32_t *)(s->arena + st.table_off + eb_bytes + sizeof(StreamJob) * (uint64_t)nd);
+        a.base = (uint64_t *)s->arena;
+        a.jobs = SJ;
+        a.njobs = nd;
+        if ((rc = launch_timed(BA_KT_OTHER, s->stream, [&] {
+                 hipLaunchKernelGGL(k_stream_batch_init, dim3(std::min<uint32_t>(nd, 1024)), dim3(256), 0, s->stream,
+                                    a);
+             })))
+            return fail_step(rc);
+        const uint32_t n16 = (uint32_t)deg16.size();
+        for (int tier = 0; tier < 2; tier++) {
+            if (!st.units[tier]) continue;
+            a.jobs = SJ + (tier ? n16 : 0);
+            a.njobs = tier ? nd - n16 : n16;
+            a.units = (uint32_t)st.units[tier];
+            a.next = next + tier;
+            const uint32_t grid = (uint32_t)std::min<uint64_t>(tier ? g64 : g16, st.units[tier]);
+            if ((rc = launch_timed(BA_KT_STREAM, s->stream, [&] {
+                     if (tier)
+                         hipLaunchKernelGGL(k_stream_batch<true>, dim3(grid), dim3(kStreamBlock), 0, s->stream, a);
+                     else
+                         hipLaunchKernelGGL(k_stream_batch<false>, dim3(grid), dim3(kStreamBlock), 0, s->stream, a);
+                 })))
+                return fail_step(rc);
+        }
+    }
+    for (uint64_t j : deg_single) {
         const ServerJob &J = *server_job(s, j);
         uint64_t *deg = (uint64_t *)(s->arena + J.out_off);
         if ((rc = ba_degrees(J.req.n, J.req.d, J.req.seed, J.req.first_k, deg, deg + J.req.first_k, s->stream)))

@@ -61,6 +61,47 @@ __device__ __forceinline__ uint64_t shalf64(uint64_t x, const Divider &v)
     return sdiv64<false>(x >> 1, v);
 }
 
+// One wave's run of tn edges starting at edge ibase: the chain of every
+// edge, its second endpoint counted (cnt: LDS counters of nodes below klds;
+// deg: global counts of nodes below k) and its checksum word XORed into xs.
+template <bool NARROW, bool POW2>
+__device__ __forceinline__ void stream_run16(const HashKey &key, const Divider &div, uint64_t ibase, uint32_t tn,
+                                             uint32_t klds, uint64_t k, uint32_t *cnt, uint64_t *deg, uint64_t &xs)
+{
+    using R = typename std::conditional<NARROW, uint32_t, uint64_t>::type;
+    chain_run_visit(
+        tn, __lane_id(), (R)(2 * ibase + 1),
+        [&](R r) -> R {
+            if constexpr (NARROW) return hash_narrow(r, key);
+            else return hash_wide(r, key);
+        },
+        [](R r) { return !((uint32_t)r & 1u); },
+        [&](R r0, R r) {  // r0 = 2i + 1, the edge's start position
+            uint64_t u, v;
+            if constexpr (NARROW) {
+                v = sdiv32<POW2>((uint32_t)r >> 1, div);
+                u = sdiv32<POW2>((uint32_t)r0 >> 1, div);
+            } else {
+                v = shalf64<POW2>(r, div);
+                u = shalf64<POW2>(r0, div);
+            }
+            if (v < klds)
+                atomicAdd(&cnt[v], 1u);
+            else if (v < k)
+                __hip_atomic_fetch_add(deg + v, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            xs ^= ((u << 32) + v) * (uint64_t)r0;
+        });
+}
+
+// The wave's checksum XORed into *cs (one atomic per wave).
+__device__ __forceinline__ void stream_xor_out(uint64_t xs, uint64_t *cs)
+{
+    if (cs) {
+        for (int o = 32; o > 0; o >>= 1) xs ^= __shfl_xor(xs, o);
+        if (__lane_id() == 0 && xs) __hip_atomic_fetch_xor(cs, xs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 template <bool NARROW, bool POW2>
 __global__ __launch_bounds__(kStreamBlock) void k_stream(StreamArgs a)
 {
@@ -68,8 +109,6 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream(StreamArgs a)
     for (uint32_t v = threadIdx.x; v < a.klds; v += kStreamBlock) cnt[v] = 0;
     __syncthreads();
 
-    using R = typename std::conditional<NARROW, uint32_t, uint64_t>::type;
-    const uint32_t lane = __lane_id();
     // wave-uniform (readfirstlane): keeps the loop control scalar
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const uint64_t gw = (uint64_t)blockIdx.x * kStreamWaves + wv;
@@ -78,34 +117,9 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream(StreamArgs a)
     if (w0 < a.count) {
         // per_wave < 2^32: the host splits larger launches
         const uint32_t tn = (uint32_t)min(a.per_wave, a.count - w0);
-        const uint64_t ibase = a.begin + w0;
-        chain_run_visit(
-            tn, lane, (R)(2 * ibase + 1),
-            [&](R r) -> R {
-                if constexpr (NARROW) return hash_narrow(r, a.key);
-                else return hash_wide(r, a.key);
-            },
-            [](R r) { return !((uint32_t)r & 1u); },
-            [&](R r0, R r) {  // r0 = 2i + 1, the edge's start position
-                uint64_t u, v;
-                if constexpr (NARROW) {
-                    v = sdiv32<POW2>((uint32_t)r >> 1, a.div);
-                    u = sdiv32<POW2>((uint32_t)r0 >> 1, a.div);
-                } else {
-                    v = shalf64<POW2>(r, a.div);
-                    u = shalf64<POW2>(r0, a.div);
-                }
-                if (v < a.klds)
-                    atomicAdd(&cnt[v], 1u);
-                else if (v < a.k)
-                    __hip_atomic_fetch_add(a.deg + v, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                xs ^= ((u << 32) + v) * (uint64_t)r0;
-            });
+        stream_run16<NARROW, POW2>(a.key, a.div, a.begin + w0, tn, a.klds, a.k, cnt, a.deg, xs);
     }
-    if (a.cs) {
-        for (int o = 32; o > 0; o >>= 1) xs ^= __shfl_xor(xs, o);
-        if (lane == 0 && xs) __hip_atomic_fetch_xor(a.cs, xs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    stream_xor_out(xs, a.cs);
     __syncthreads();
     for (uint32_t v = threadIdx.x; v < a.klds; v += kStreamBlock) {
         const uint32_t c = cnt[v];
@@ -133,24 +147,34 @@ constexpr uint32_t kPackedNodes = 65536;
 constexpr uint32_t kStreamRoundClaims = 1920;
 static_assert(kStreamWaves * (kStreamRoundClaims + 2 * kWave - 1) <= 0x8000, "a round must not wrap a 16-bit counter");
 
-template <bool NARROW, bool POW2>
-__global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
+// The packed counters of nodes below ktier added to deg (and cleared, for
+// the next unit of a batched launch).
+__device__ __forceinline__ void packed_flush(uint32_t *cnt, uint32_t ktier, uint64_t *deg)
 {
-    __shared__ uint32_t cnt[kPackedNodes / 2];  // node v: word v >> 1, half v & 1
-    for (uint32_t w = threadIdx.x; w < kPackedNodes / 2; w += kStreamBlock) cnt[w] = 0;
-    __syncthreads();
+    for (uint32_t w = threadIdx.x; w < kPackedNodes / 2; w += kStreamBlock) {
+        const uint32_t c = cnt[w];
+        cnt[w] = 0;
+        const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
+        if (lo && 2 * w < ktier)
+            __hip_atomic_fetch_add(deg + 2 * w, (uint64_t)lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (hi && 2 * w + 1 < ktier)
+            __hip_atomic_fetch_add(deg + 2 * w + 1, (uint64_t)hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// One wave's run of tot edges starting at edge ibase on the 64K tier (see
+// above): two chains per lane, counts of nodes below ktier in the packed
+// LDS counters cnt, of nodes below k in deg, checksum words into xs.  The
+// wave takes exactly `rounds` block barriers (at least its own claims /
+// kStreamRoundClaims), so every wave of the block must pass the same rounds.
+template <bool NARROW, bool POW2>
+__device__ __forceinline__ void stream_run_packed(const HashKey &key, const Divider &div, uint64_t ibase, uint32_t tot,
+                                                  uint32_t ktier, uint64_t k, uint32_t *cnt, uint64_t *deg,
+                                                  uint64_t rounds, uint64_t &xs)
+{
     using R = typename std::conditional<NARROW, uint32_t, uint64_t>::type;
     const uint32_t lane = __lane_id();
-    // wave-uniform (readfirstlane): keeps the loop control scalar
-    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const uint64_t gw = (uint64_t)blockIdx.x * kStreamWaves + wv;
-    const uint64_t w0 = gw * a.per_wave;
-    // edges of this wave (per_wave < 2^32: the host splits larger launches)
-    const uint32_t tot = w0 < a.count ? (uint32_t)min(a.per_wave, a.count - w0) : 0u;
-    const uint64_t ibase = a.begin + w0;
     const R rbase = (R)(2 * ibase + 1);
-    const uint32_t ktier = a.klds;  // min(first_k, 65536)
-    uint64_t xs = 0;
 
     // The value a lane's last LDS increment returned is examined at its next
     // finished edge of the same chain (or before its wave's next barrier),
@@ -162,32 +186,32 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
             const uint32_t sh = (pend_v & 1u) << 4;
             if (((pend_old >> sh) & 0xFFFFu) == 0x7FFFu) {
                 atomicSub(&cnt[pend_v >> 1], 0x8000u << sh);
-                __hip_atomic_fetch_add(a.deg + pend_v, (uint64_t)0x8000, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(deg + pend_v, (uint64_t)0x8000, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             pend_v = kNone;
         }
     };
     auto hash = [&](R r) -> R {
-        if constexpr (NARROW) return hash_narrow(r, a.key);
-        else return hash_wide(r, a.key);
+        if constexpr (NARROW) return hash_narrow(r, key);
+        else return hash_wide(r, key);
     };
     // r0 = 2i + 1: the edge's start position (i = r0 >> 1, and the checksum
     // multiplier itself)
     auto finish = [&](R r0, R r, uint32_t &pend_old, uint32_t &pend_v) {
         uint64_t u, v;
         if constexpr (NARROW) {
-            v = sdiv32<POW2>((uint32_t)r >> 1, a.div);
-            u = sdiv32<POW2>((uint32_t)r0 >> 1, a.div);
+            v = sdiv32<POW2>((uint32_t)r >> 1, div);
+            u = sdiv32<POW2>((uint32_t)r0 >> 1, div);
         } else {
-            v = shalf64<POW2>(r, a.div);
-            u = shalf64<POW2>(r0, a.div);
+            v = shalf64<POW2>(r, div);
+            u = shalf64<POW2>(r0, div);
         }
         settle(pend_old, pend_v);
         if (v < ktier) {
             pend_old = atomicAdd(&cnt[(uint32_t)v >> 1], 1u << (((uint32_t)v & 1u) << 4));
             pend_v = (uint32_t)v;
-        } else if (v < a.k) {
-            __hip_atomic_fetch_add(a.deg + v, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (v < k) {
+            __hip_atomic_fetch_add(deg + v, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         xs ^= ((u << 32) + v) * (uint64_t)r0;
     };
@@ -264,20 +288,135 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
     }
     settle(pa_old, pa_v);
     settle(pb_old, pb_v);
-    for (; bars < a.rounds; bars++) lds_barrier();
+    for (; bars < rounds; bars++) lds_barrier();
+}
 
-    if (a.cs) {
-        for (int o = 32; o > 0; o >>= 1) xs ^= __shfl_xor(xs, o);
-        if (lane == 0 && xs) __hip_atomic_fetch_xor(a.cs, xs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+template <bool NARROW, bool POW2>
+__global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
+{
+    __shared__ uint32_t cnt[kPackedNodes / 2];  // node v: word v >> 1, half v & 1
+    for (uint32_t w = threadIdx.x; w < kPackedNodes / 2; w += kStreamBlock) cnt[w] = 0;
     __syncthreads();
-    for (uint32_t w = threadIdx.x; w < kPackedNodes / 2; w += kStreamBlock) {
-        const uint32_t c = cnt[w];
-        const uint32_t lo = c & 0xFFFFu, hi = c >> 16;
-        if (lo && 2 * w < ktier)
-            __hip_atomic_fetch_add(a.deg + 2 * w, (uint64_t)lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (hi && 2 * w + 1 < ktier)
-            __hip_atomic_fetch_add(a.deg + 2 * w + 1, (uint64_t)hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // wave-uniform (readfirstlane): keeps the loop control scalar
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const uint64_t gw = (uint64_t)blockIdx.x * kStreamWaves + wv;
+    const uint64_t w0 = gw * a.per_wave;
+    // edges of this wave (per_wave < 2^32: the host splits larger launches)
+    const uint32_t tot = w0 < a.count ? (uint32_t)min(a.per_wave, a.count - w0) : 0u;
+    const uint32_t ktier = a.klds;  // min(first_k, 65536)
+    uint64_t xs = 0;
+    stream_run_packed<NARROW, POW2>(a.key, a.div, a.begin + w0, tot, ktier, a.k, cnt, a.deg, a.rounds, xs);
+    stream_xor_out(xs, a.cs);
+    __syncthreads();
+    packed_flush(cnt, ktier, a.deg);
+}
+
+// ---------------------------------------------------------------------------
+// Batched streaming: many degree requests (graphs) in one persistent launch,
+// for the served path.  Each request j is cut into units of kStreamWaves
+// wave runs of jobs[j].per_wave edges; blocks take units from a device
+// counter in table order (the host lists the requests with the longest runs
+// first), so one block works on one request at a time: its waves run the
+// unit's edges into the block's LDS table, which is then added to that
+// request's degrees and cleared.  Results do not depend on which block takes
+// which unit (counts are added, checksum words XORed).
+
+struct StreamJob {
+    HashKey key;
+    uint32_t narrow;    // every position of the graph below 2^32
+    Divider div;
+    uint64_t m;         // edges of the graph
+    uint64_t k;         // first_k
+    uint64_t out;       // uint64 elements from the launch's base: k degrees, then the checksum
+    uint64_t per_wave;  // edges per wave run (a multiple of 64; 64K tier: of kStreamRoundClaims too)
+    uint64_t unit0;     // the request's first unit
+    uint64_t rounds;    // 64K tier: block barriers per unit
+};
+
+struct StreamBatchArgs {
+    const StreamJob *jobs;
+    uint32_t njobs;
+    uint32_t units;     // units of all requests
+    uint32_t *next;     // next unit to take (zero at launch)
+    uint64_t *base;     // outputs
+};
+
+// deg = d for each request's nodes below first_k (their first endpoints, in
+// closed form) and checksum = 0, before the batched streaming launch.
+__global__ __launch_bounds__(256) void k_stream_batch_init(StreamBatchArgs a)
+{
+    for (uint32_t j = blockIdx.x; j < a.njobs; j += gridDim.x) {
+        const StreamJob J = a.jobs[j];
+        uint64_t *deg = a.base + J.out;
+        const uint64_t d = J.div.d;
+        for (uint64_t v = threadIdx.x; v < J.k; v += 256) deg[v] = J.m ? d : 0;
+        if (threadIdx.x == 0) deg[J.k] = 0;
+    }
+}
+
+// Requests of one batched streaming launch at most: their first units are
+// cached in LDS (16 KB beside the 64 KB table keeps two 16K-tier blocks per
+// compute unit).
+constexpr uint32_t kStreamBatchJobs = 4000;
+
+template <bool PACKED>
+__global__ __launch_bounds__(kStreamBlock) void k_stream_batch(StreamBatchArgs a)
+{
+    constexpr uint32_t kWords = PACKED ? kPackedNodes / 2 : kLdsNodes;
+    __shared__ uint32_t cnt[kWords];
+    __shared__ uint32_t unit0[kStreamBatchJobs];  // first unit of each request (the search runs in LDS)
+    __shared__ uint32_t unit_sh;
+    for (uint32_t w = threadIdx.x; w < kWords; w += kStreamBlock) cnt[w] = 0;
+    for (uint32_t j = threadIdx.x; j < a.njobs; j += kStreamBlock) unit0[j] = (uint32_t)a.jobs[j].unit0;
+    if (threadIdx.x == 0) unit_sh = atomicAdd(a.next, 1u);
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    for (;;) {
+        __syncthreads();
+        const uint32_t u = __builtin_amdgcn_readfirstlane(unit_sh);
+        if (u >= a.units) break;  // every wave sees the same u: the whole block leaves
+        // the next unit is taken now; its index is needed only after this one
+        uint32_t u_next = 0;
+        if (threadIdx.x == 0) u_next = atomicAdd(a.next, 1u);
+        uint32_t lo = 0, hi = a.njobs;  // the request j with unit0[j] <= u < unit0[j+1]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (unit0[mid] <= u) lo = mid; else hi = mid;
+        }
+        const uint32_t j = __builtin_amdgcn_readfirstlane(lo);
+        // a copy: the hot loop stores to global memory, so fields read through
+        // a reference would be reloaded after every degree update
+        const StreamJob J = a.jobs[j];
+        const uint64_t w0 = ((u - J.unit0) * (uint64_t)kStreamWaves + wv) * J.per_wave;
+        const uint32_t tn = w0 < J.m ? (uint32_t)min(J.per_wave, J.m - w0) : 0u;
+        const uint32_t klds = (uint32_t)min(J.k, (uint64_t)(PACKED ? kPackedNodes : kLdsNodes));
+        uint64_t *deg = a.base + J.out;
+        uint64_t xs = 0;
+        auto run = [&](auto n_t, auto p_t) {
+            constexpr bool N = decltype(n_t)::value, P = decltype(p_t)::value;
+            if constexpr (PACKED)
+                stream_run_packed<N, P>(J.key, J.div, w0, tn, klds, J.k, cnt, deg, J.rounds, xs);
+            else if (tn)
+                stream_run16<N, P>(J.key, J.div, w0, tn, klds, J.k, cnt, deg, xs);
+        };
+        using T = std::true_type;
+        using F = std::false_type;
+        if (J.narrow) {
+            if (J.div.pow2) run(T{}, T{}); else run(T{}, F{});
+        } else {
+            if (J.div.pow2) run(F{}, T{}); else run(F{}, F{});
+        }
+        stream_xor_out(xs, deg + J.k);
+        __syncthreads();  // every wave has read unit_sh and counted its run
+        if (threadIdx.x == 0) unit_sh = u_next;
+        if constexpr (PACKED) {
+            packed_flush(cnt, klds, deg);
+        } else {
+            for (uint32_t v = threadIdx.x; v < klds; v += kStreamBlock) {
+                const uint32_t c = cnt[v];
+                cnt[v] = 0;
+                if (c) __hip_atomic_fetch_add(deg + v, (uint64_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
     }
 }
 
