@@ -52,7 +52,8 @@ namespace ba {
 constexpr int kWave = 64;
 constexpr int kGenBlock = 256;  // 4 waves
 constexpr int kGenWaves = kGenBlock / kWave;
-constexpr uint32_t kTile = 1024;  // edges per wave tile (4 KiB of LDS per wave; 8 waves/SIMD fit)
+constexpr uint32_t kTile = 1024;  // edges per wave tile (4 KiB of LDS per wave)
+constexpr uint32_t kGenCarry = 192;  // next-tile edges a wave's chain tail may claim (8 waves/SIMD still fit)
 
 struct GenArgs {
     HashKey key;
@@ -292,6 +293,88 @@ __device__ __forceinline__ void chain_tile(uint32_t *stage, uint32_t tn, uint32_
     chain_tile_until(stage, tn, lane, rbase, hash, [](R r) { return !((uint32_t)r & 1u); }, out);
 }
 
+// Chain-loop state a wave carries from one of its tiles into its next
+// (chain_tile_carry): the next tile's first ncl edges are claimed; a lane
+// still running one of them keeps its position and its index there, and
+// the results of those that already finished wait in the wave's side buffer.
+constexpr uint32_t kIdle = 0xFFFFFFFFu;
+template <class R>
+struct ChainCarry {
+    R r;               // per lane: the chain's current position (valid iff li < ncl)
+    uint32_t li;       // per lane: index of its edge in the next tile, or kIdle
+    uint32_t ncl = 0;  // wave-uniform: edges of the next tile claimed (a prefix)
+};
+
+// chain_tile of the plain model with the tail filled from the wave's next
+// tile (tn2 edges from position rbase2; none if tn2 = 0).  Once every edge
+// of this tile is claimed, a finishing lane takes the next unclaimed edge of
+// the next tile, at most CAP of them, instead of idling while the tile's
+// last chains run; a finished next-tile edge stores its result at
+// side[index].  The call for the next tile, with the same carry, copies
+// those into its stage and resumes the chains still running.  Every edge's
+// result lands at the same stage slot as with chain_tile, so the order in
+// which chains run changes nothing downstream.
+template <uint32_t CAP, class R, class H, class O>
+__device__ __forceinline__ void chain_tile_carry(uint32_t *stage, uint32_t *side, uint32_t tn, uint32_t lane,
+                                                 R rbase, uint32_t tn2, R rbase2, H hash, O out, ChainCarry<R> &c)
+{
+    tn = wave_uniform(tn);
+    const uint32_t ncl = wave_uniform(c.ncl);  // <= tn: at most min(tn, CAP) were claimed
+    for (uint32_t j = lane; j < ncl; j += kWave) stage[j] = side[j];  // slots of running chains: rewritten later
+    // Edges in one index space: li < tn this tile, tn <= li < lim the next one.
+    const uint32_t lim = tn + min(wave_uniform(tn2), CAP);
+    const R rb2 = wave_uniform((R)(rbase2 - 2 * (R)tn));  // start position of index li >= tn: rb2 + 2 li
+    const uint32_t sbase = wave_uniform((uint32_t)(uintptr_t)(lds_u32 *)stage);    // LDS byte address of slot 0
+    const uint32_t xbase = wave_uniform((uint32_t)(uintptr_t)(lds_u32 *)side) - 4 * tn;  // of index li >= tn: xbase + 4 li
+    // lanes without a running chain claim ncl, ncl+1, ...
+    const bool held = c.li < ncl;
+    const uint64_t fm = __ballot(!held);
+    uint32_t li = c.li;
+    R r = c.r;
+    if (!held) {
+        li = ncl + lane_rank(fm);
+        r = (li < tn ? rbase : rb2) + 2 * (R)li;
+    }
+    uint32_t next = ncl + (uint32_t)__popcll(fm);  // next unclaimed index (wave-uniform)
+    if (next + kWave <= tn) {
+        // every lane's edge is in this tile (li < next): the steady loop of chain_tile_until
+        uint32_t sa = sbase + 4 * li;
+        do {
+            r = hash(r);
+            const bool fin = !((uint32_t)r & 1u);
+            const uint64_t dm = __ballot(fin);
+            if (fin) {
+                *(lds_u32 *)(uintptr_t)sa = out(r);
+                const uint32_t k = lane_rank(dm);
+                sa = wave_uniform(sbase + 4 * next) + 4 * k;
+                r = wave_uniform((R)(rbase + 2 * (R)next)) + 2 * (R)k;
+            }
+            next += (uint32_t)__popcll(dm);
+        } while (next + kWave <= tn);
+        li = (sa - sbase) >> 2;
+    }
+    // tail: runs until no lane holds an edge of this tile; a lane is live iff li < lim
+    uint64_t cur = __ballot(li < tn);
+    uint64_t live = __ballot(li < lim);
+    while (cur) {
+        r = hash(r);
+        const bool fin = !((uint32_t)r & 1u);
+        const uint64_t dm = __ballot(fin) & live;
+        if (fin && li < lim) {
+            *(lds_u32 *)(uintptr_t)((li < tn ? sbase : xbase) + 4 * li) = out(r);
+            li = next + lane_rank(dm);  // >= lim: idle until the next call
+            r = (li < tn ? rbase : rb2) + 2 * (R)li;
+        }
+        next += (uint32_t)__popcll(dm);
+        cur = __ballot(li < tn);
+        live = __ballot(li < lim);
+    }
+    // every index below tn was claimed (a finishing lane takes the lowest unclaimed one)
+    c.ncl = min(next, lim) - tn;
+    c.li = li < lim ? li - tn : kIdle;
+    c.r = r;
+}
+
 // One chain step for every lane, then refill of the lanes that finished.
 // NARROW: all positions of the launch are below 2^32.  DM: the second
 // endpoints also go to the degree pipeline's target list (kDegList), or are
@@ -301,22 +384,33 @@ template <bool NARROW, bool VEC16, int DM>
 __global__ __launch_bounds__(kGenBlock) void k_gen_u32(GenArgs a)
 {
     __shared__ uint32_t stage_all[kGenWaves][kTile];
+    __shared__ uint32_t side_all[kGenWaves][kGenCarry];  // next-tile results of a wave's chain tail
     const uint32_t lane = __lane_id();
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform: scalar tile bases
     uint32_t *stage = stage_all[wv];
     const uint64_t wstride = (uint64_t)gridDim.x * kGenWaves;
+    using R = std::conditional_t<NARROW, uint32_t, uint64_t>;
+    ChainCarry<R> cc;
+    cc.li = kIdle;
 
     for (uint64_t tile = (uint64_t)blockIdx.x * kGenWaves + wv; tile < a.ntiles; tile += wstride) {
         const uint64_t off = tile * kTile;
         const uint32_t tn = (uint32_t)min((uint64_t)kTile, a.count - off);
         const uint64_t ibase = a.begin + off;
+        // the wave's next tile, which its chain tail runs into
+        const uint64_t off2 = (tile + wstride) * kTile;
+        const uint32_t tn2 = tile + wstride < a.ntiles ? (uint32_t)min((uint64_t)kTile, a.count - off2) : 0u;
 
         if constexpr (NARROW)
-            chain_tile(stage, tn, lane, (uint32_t)(2 * ibase + 1), [&](uint32_t r) { return hash_narrow(r, a.key); },
-                       [](uint32_t r) { return r; });
+            chain_tile_carry<kGenCarry>(stage, side_all[wv], tn, lane, (R)(2 * ibase + 1), tn2,
+                                        (R)(2 * (a.begin + off2) + 1),
+                                        [&](uint32_t r) { return hash_narrow(r, a.key); },
+                                        [](uint32_t r) { return r; }, cc);
         else
-            chain_tile(stage, tn, lane, 2 * ibase + 1, [&](uint64_t r) { return hash_wide(r, a.key); },
-                       [&](uint64_t r) { return (uint32_t)div64(r >> 1, a.div); });
+            chain_tile_carry<kGenCarry>(stage, side_all[wv], tn, lane, (R)(2 * ibase + 1), tn2,
+                                        (R)(2 * (a.begin + off2) + 1),
+                                        [&](uint64_t r) { return hash_wide(r, a.key); },
+                                        [&](uint64_t r) { return (uint32_t)div64(r >> 1, a.div); }, cc);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -605,7 +699,7 @@ static int deg_count(const DegArgs &a, uint64_t count, hipStream_t st)
         return rc;
     if ((rc = launch_timed(BA_KT_OTHER, st, [&] { hipLaunchKernelGGL(k_deg_scan, dim3(1), dim3(1024), 0, st, a); })))
         return rc;
-    const uint32_t parts_max = (uint32_t)((uint64_t)a.p.NBsub + (count + kHPart - 1) / kHPart + 1);
+    const uint32_t parts_max = (uint32_t)((uint64_t)a.p.NBsub + (count + a.p.H - 1) / a.p.H + 1);
     if ((rc = launch_timed(BA_KT_HIST, st, [&] {
              if (a.p.S == kS16)
                  hipLaunchKernelGGL(k_deg_hist16, dim3(parts_max), dim3(kHBlock), 0, st, a);

@@ -53,7 +53,8 @@ constexpr uint32_t kPBlock = 1024;
 constexpr uint32_t kPPer = 20;                  // edges per thread per chunk
 constexpr uint32_t kPChunk = kPBlock * kPPer;   // 20480 edges per chunk
 constexpr uint32_t kPBlocksMax = 1024;          // partition blocks a layout allows
-constexpr uint32_t kHPart = 1u << 20;           // entries per count part (target)
+constexpr uint32_t kHPartMin = 1u << 20;        // entries per count part, at least
+constexpr uint32_t kHParts = 256;               // count parts a pass aims at (one per compute unit)
 constexpr uint32_t kHBlock = 1024;
 constexpr uint64_t kPieceMax = 1ull << 31;      // edges per pipeline pass
 constexpr uint64_t kPieceMin = 1ull << 20;
@@ -102,6 +103,8 @@ struct DegPlan {
     uint32_t fused;  // n <= 2^26: the generator partitions its own targets into 65536-node sub-buckets
                      // (no target list); else the partition kernel, 32768-node sub-buckets in windows
     uint32_t S;      // sub-bucket shift: 16 (fused) or 15
+    uint32_t H;      // entries per count part (target): a sub-bucket of t entries is counted by
+                     // ceil(t / H) blocks, whose counts meet in deg by global atomics
     uint64_t n, C;
     uint64_t A;  // region entries reserved in the layout
     uint64_t o_V, o_rcap, o_off, o_fill, o_tot, o_parts, o_partoff, o_flag, o_L, bytes;
@@ -117,6 +120,12 @@ static inline DegPlan make_deg_plan(uint64_t n, uint64_t C, uint32_t P)
     p.P = P;
     p.fused = n <= ((uint64_t)kWin16 << kS16) ? 1u : 0u;
     p.S = p.fused ? kS16 : kS2;
+    // Parts about as large as one compute unit's share of the pass: fewer
+    // parts mean fewer global atomics when their counts meet (each part of
+    // a sub-bucket adds its whole counter array), while no part may hold
+    // much more than a unit's share, or it alone sets the histogram's time
+    // (the lowest sub-buckets draw the most targets).
+    p.H = (uint32_t)std::max<uint64_t>(kHPartMin, C / kHParts);
     p.NBsub = (uint32_t)((n + ((uint64_t)1 << p.S) - 1) >> p.S);
     if (p.NBsub == 0) p.NBsub = 1;
     p.NW = p.fused ? 1u : (p.NBsub + kWin - 1) / kWin;
@@ -392,7 +401,7 @@ __global__ __launch_bounds__(256) void k_deg_tot(DegArgs a)
     if (threadIdx.x == 0) {
         const uint32_t t = sh[0] + sh[1] + sh[2] + sh[3];
         ws_tot(a)[g] = t;
-        uint32_t np = (t + kHPart - 1) / kHPart;
+        uint32_t np = (uint32_t)(((uint64_t)t + a.p.H - 1) / a.p.H);
         if (np > a.p.P) np = a.p.P;
         ws_parts(a)[g] = np;
     }

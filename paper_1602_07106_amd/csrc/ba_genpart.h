@@ -12,6 +12,9 @@
 // indices to the block's own region for it, exactly the layout k_deg_part
 // builds from the target list; the totals, scan and histogram kernels of
 // ba_degree.h then finish the degrees.  No target list is written or read.
+// Each wave writes out the sorted entries that sit in its own stage part and
+// goes on to its next chunk without waiting for the block, and its chain
+// tail runs into the wave's tile of that chunk (chain_tile_carry).
 //
 // Run length is what matters for the sort: a chunk's 22528 second endpoints
 // over 1024 sub-buckets leave runs of about 22 entries (44 bytes) per region
@@ -23,11 +26,12 @@
 namespace ba {
 
 constexpr uint32_t kFWaves = 16;
-constexpr uint32_t kFBlock = kFWaves * kWave;   // 1024 threads, one block per compute unit (120 KiB of LDS)
+constexpr uint32_t kFBlock = kFWaves * kWave;   // 1024 threads, one block per compute unit (121 KiB of LDS)
 constexpr uint32_t kFTile = 1408;               // edges per wave per chunk (a multiple of 128)
 constexpr uint32_t kFChunk = kFWaves * kFTile;  // 22528 edges per block chunk
 constexpr uint32_t kFPer = kFTile / kWave;      // second endpoints per thread
 constexpr uint32_t kFBins = kWin16 / kFBlock;   // sub-buckets per thread in the scan
+constexpr uint32_t kFCarry = 256;               // next-tile edges a wave's chain tail may claim
 static_assert(kFTile % (2 * kWave) == 0 && kFPer % 2 == 0, "pair flush");
 static_assert(kFChunk < 65536, "16-bit ranks");
 static_assert(kWin16 % kFBlock == 0, "scan");
@@ -49,6 +53,7 @@ __global__ __launch_bounds__(kFBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
     __shared__ uint32_t dlx[kWin16];          // per chunk: region slot of sorted entry x is dlx[b] + x
     __shared__ uint32_t scan_sh[16];
     __shared__ uint32_t any_over;           // per chunk: some region of this block is full
+    __shared__ uint32_t side_all[kFWaves][kFCarry];  // per wave: next-tile results of the chain tail
     const DegArgs &q = a.p;
     const uint32_t nb = q.p.NBsub;  // <= kWin16
     const uint32_t blk = blockIdx.x, P = gridDim.x;
@@ -62,22 +67,35 @@ __global__ __launch_bounds__(kFBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
     const uint32_t lane = __lane_id();
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform: scalar tile bases
     uint32_t *st_w = stage + wv * kFTile;
+    uint32_t *side_w = side_all[wv];
+    using R = std::conditional_t<NARROW, uint32_t, uint64_t>;
+    ChainCarry<R> cc;
+    cc.li = kIdle;
+    // this wave's tile of chunk ch: first edge offset and size
+    auto tile_of = [&](uint64_t ch, uint64_t &woff) -> uint32_t {
+        woff = ch * kFChunk + (uint64_t)wv * kFTile;
+        return ch < a.nchunks && woff < a.g.count ? (uint32_t)min((uint64_t)kFTile, a.g.count - woff) : 0u;
+    };
 
     for (uint64_t ch = blk; ch < a.nchunks; ch += P) {
         // ---- this wave's edges of the chunk: chain loop, edge pairs out
-        const uint64_t woff = ch * kFChunk + (uint64_t)wv * kFTile;
-        const uint32_t tn = woff < a.g.count ? (uint32_t)min((uint64_t)kFTile, a.g.count - woff) : 0u;
+        uint64_t woff, woff2;
+        const uint32_t tn = tile_of(ch, woff);
+        const uint32_t tn2 = tile_of(ch + P, woff2);  // the wave's tile of its next chunk (its tail runs into it)
         const uint64_t ibase = a.g.begin + woff;
+        const R rbase = (R)(2 * ibase + 1), rbase2 = (R)(2 * (a.g.begin + woff2) + 1);
         uint32_t v[kFPer];
 #pragma unroll
         for (uint32_t t = 0; t < kFPer; t++) v[t] = kOut;
         if (tn) {
             if constexpr (NARROW)
-                chain_tile(st_w, tn, lane, (uint32_t)(2 * ibase + 1),
-                           [&](uint32_t r) { return hash_narrow(r, a.g.key); }, [](uint32_t r) { return r; });
+                chain_tile_carry<kFCarry>(st_w, side_w, tn, lane, rbase, tn2, rbase2,
+                                          [&](uint32_t r) { return hash_narrow(r, a.g.key); },
+                                          [](uint32_t r) { return r; }, cc);
             else
-                chain_tile(st_w, tn, lane, 2 * ibase + 1, [&](uint64_t r) { return hash_wide(r, a.g.key); },
-                           [&](uint64_t r) { return (uint32_t)fdiv64<POW2>(r >> 1, a.g.div); });
+                chain_tile_carry<kFCarry>(st_w, side_w, tn, lane, rbase, tn2, rbase2,
+                                          [&](uint64_t r) { return hash_wide(r, a.g.key); },
+                                          [&](uint64_t r) { return (uint32_t)fdiv64<POW2>(r >> 1, a.g.div); }, cc);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -161,35 +179,43 @@ __global__ __launch_bounds__(kFBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
             }
         }
         lds_barrier();
-        // sorted runs out: consecutive threads take consecutive sorted entries,
-        // so a store covers a few runs of contiguous region slots
+        // Sorted runs out.  Wave w takes the sorted entries of its own stage
+        // part, consecutive lanes consecutive entries, so a store covers a
+        // few runs of contiguous region slots.  It then goes straight on to
+        // its next chain loop, which rewrites only that part: no block
+        // barrier ends the chunk (the next chunk's sort rewrites dlx, wpos
+        // and any_over only behind its first barrier, when every wave is done
+        // here).
         const bool over = any_over != 0;
-        for (uint32_t x0 = threadIdx.x; x0 < total; x0 += 4 * kFBlock) {
-            uint32_t w[4], t[4];
+        const uint32_t x0 = wv * kFTile;
+        if (!over && x0 + kFTile <= total) {  // no region full, a whole part (the normal case)
+            constexpr uint32_t G = 2;  // entries a lane loads before it stores (more gains nothing)
+            static_assert(kFPer % G == 0, "whole groups");
+#pragma unroll 1
+            for (uint32_t t0 = 0; t0 < kFPer; t0 += G) {
+                uint32_t w[G], o[G];
 #pragma unroll
-            for (uint32_t u = 0; u < 4; u++) w[u] = x0 + u * kFBlock < total ? stage[x0 + u * kFBlock] : 0u;
+                for (uint32_t u = 0; u < G; u++) w[u] = st_w[(t0 + u) * kWave + lane];
 #pragma unroll
-            for (uint32_t u = 0; u < 4; u++) t[u] = dlx[w[u] >> kS16];
-            if (!over) {  // no region full in this chunk (the normal case)
+                for (uint32_t u = 0; u < G; u++) o[u] = dlx[w[u] >> kS16];
 #pragma unroll
-                for (uint32_t u = 0; u < 4; u++)
-                    if (x0 + u * kFBlock < total) L[t[u] + x0 + u * kFBlock] = (uint16_t)(w[u] & (kSub16 - 1));
-            } else {
-                if (x0 == 0) *ws_flag(q) = 1;  // deg takes atomics before the histogram
-#pragma unroll
-                for (uint32_t u = 0; u < 4; u++) {
-                    const uint32_t x = x0 + u * kFBlock;
-                    if (x < total) {
-                        const uint32_t slot = t[u] + x;
-                        if (slot < wend[w[u] >> kS16])
-                            L[slot] = (uint16_t)(w[u] & (kSub16 - 1));
-                        else
-                            deg_atomic_add(q.deg, w[u], 1u);
-                    }
+                for (uint32_t u = 0; u < G; u++)
+                    L[o[u] + x0 + (t0 + u) * kWave + lane] = (uint16_t)(w[u] & (kSub16 - 1));
+            }
+        } else if (x0 < total) {
+            if (over && wv == 0 && lane == 0) *ws_flag(q) = 1;  // deg takes atomics before the histogram
+            for (uint32_t t = 0; t < kFPer; t++) {
+                const uint32_t x = x0 + t * kWave + lane;
+                if (x < total) {
+                    const uint32_t w = stage[x];
+                    const uint32_t slot = dlx[w >> kS16] + x;
+                    if (!over || slot < wend[w >> kS16])
+                        L[slot] = (uint16_t)(w & (kSub16 - 1));
+                    else
+                        deg_atomic_add(q.deg, w, 1u);
                 }
             }
         }
-        lds_barrier();  // the stage is free for the next chunk's chain loop
     }
     // this block's fill per sub-bucket (k_deg_tot caps it at the region size)
     uint32_t *gfill = ws_fill(q) + (uint64_t)blk * nb;
