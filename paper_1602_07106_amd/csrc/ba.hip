@@ -375,6 +375,72 @@ __device__ __forceinline__ void chain_tile_carry(uint32_t *stage, uint32_t *side
     c.r = r;
 }
 
+// chain_tile_carry for a wave whose next tile (tn2 edges, none if 0) starts
+// right after this one in edge IDs, with room for CAP more slots after the
+// tile's in its stage (stage[tn .. tn+CAP)).  Index li is then edge li of
+// this tile or, from tn on, of the next one, with one slot address and one
+// start position formula for both: the tail claims next-tile edges with the
+// steady loop's own refill, and costs one compare per step more than it
+// (the test whether a lane still holds an edge of this tile).  The next call
+// moves the early results (c.off on) to the front of its stage.
+template <uint32_t CAP, class R, class H, class O>
+__device__ __forceinline__ void chain_tile_next(uint32_t *stage, uint32_t tn, uint32_t tn2, uint32_t lane, R rbase,
+                                                H hash, O out, ChainCarry<R> &c, uint32_t &coff)
+{
+    tn = wave_uniform(tn);
+    const uint32_t ncl = wave_uniform(c.ncl);  // <= min(tn, CAP)
+    const uint32_t src = wave_uniform(coff);
+    for (uint32_t j = lane; j < ncl; j += kWave) stage[j] = stage[src + j];  // slots of running chains: rewritten later
+    const uint32_t lim = tn + min(wave_uniform(tn2), CAP);
+    const uint32_t sbase = wave_uniform((uint32_t)(uintptr_t)(lds_u32 *)stage);  // LDS byte address of slot 0
+    const uint32_t send = sbase + 4 * tn;                                        // of the tile's end
+    // lanes without a running chain claim ncl, ncl+1, ...
+    const bool held = c.li < ncl;
+    const uint64_t fm = __ballot(!held);
+    uint32_t li = held ? c.li : ncl + lane_rank(fm);
+    R r = held ? c.r : rbase + 2 * (R)li;
+    uint32_t sa = sbase + 4 * li;
+    uint32_t next = ncl + (uint32_t)__popcll(fm);  // next unclaimed index (wave-uniform)
+    auto step = [&] {  // one step of every lane; refill from `next` (no lane may claim past lim)
+        r = hash(r);
+        const bool fin = !((uint32_t)r & 1u);
+        const uint64_t dm = __ballot(fin);
+        if (fin) {
+            *(lds_u32 *)(uintptr_t)sa = out(r);
+            const uint32_t k = lane_rank(dm);
+            sa = wave_uniform(sbase + 4 * next) + 4 * k;
+            r = wave_uniform((R)(rbase + 2 * (R)next)) + 2 * (R)k;
+        }
+        next += (uint32_t)__popcll(dm);
+    };
+    // steady loop: every lane's edge is in this tile (li < next <= tn)
+    while (next + kWave <= tn) step();
+    // tail while no claim can reach lim: every lane holds an edge below lim;
+    // it ends once no lane holds one of this tile
+    while (next + kWave <= lim && __ballot(sa < send)) step();
+    // general tail (the claims reached lim): a lane is live iff li < lim
+    li = (sa - sbase) >> 2;
+    uint64_t cur = __ballot(li < tn);
+    uint64_t live = __ballot(li < lim);
+    while (cur) {
+        r = hash(r);
+        const bool fin = !((uint32_t)r & 1u);
+        const uint64_t dm = __ballot(fin) & live;
+        if (fin && li < lim) {
+            stage[li] = out(r);
+            li = next + lane_rank(dm);  // >= lim: idle until the next call
+            r = rbase + 2 * (R)li;
+        }
+        next += (uint32_t)__popcll(dm);
+        cur = __ballot(li < tn);
+        live = __ballot(li < lim);
+    }
+    c.ncl = min(next, lim) - tn;
+    c.li = li < lim ? li - tn : kIdle;
+    c.r = r;
+    coff = tn;
+}
+
 // One chain step for every lane, then refill of the lanes that finished.
 // NARROW: all positions of the launch are below 2^32.  DM: the second
 // endpoints also go to the degree pipeline's target list (kDegList), or are
@@ -383,34 +449,34 @@ __device__ __forceinline__ void chain_tile_carry(uint32_t *stage, uint32_t *side
 template <bool NARROW, bool VEC16, int DM>
 __global__ __launch_bounds__(kGenBlock) void k_gen_u32(GenArgs a)
 {
-    __shared__ uint32_t stage_all[kGenWaves][kTile];
-    __shared__ uint32_t side_all[kGenWaves][kGenCarry];  // next-tile results of a wave's chain tail
+    __shared__ uint32_t stage_all[kGenWaves][kTile + kGenCarry];  // a tile, then next-tile results of its tail
     const uint32_t lane = __lane_id();
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform: scalar tile bases
     uint32_t *stage = stage_all[wv];
-    const uint64_t wstride = (uint64_t)gridDim.x * kGenWaves;
+    // wave w takes tiles t0 .. t1-1, consecutive in edge IDs, so the chain
+    // tail of one tile runs straight into the next
+    const uint64_t nw = (uint64_t)gridDim.x * kGenWaves, w = (uint64_t)blockIdx.x * kGenWaves + wv;
+    const uint64_t per = a.ntiles / nw, extra = a.ntiles % nw;
+    const uint64_t t0 = w * per + min(w, extra), t1 = t0 + per + (w < extra ? 1u : 0u);
     using R = std::conditional_t<NARROW, uint32_t, uint64_t>;
     ChainCarry<R> cc;
     cc.li = kIdle;
+    uint32_t coff = 0;
 
-    for (uint64_t tile = (uint64_t)blockIdx.x * kGenWaves + wv; tile < a.ntiles; tile += wstride) {
+    for (uint64_t tile = t0; tile < t1; tile++) {
         const uint64_t off = tile * kTile;
         const uint32_t tn = (uint32_t)min((uint64_t)kTile, a.count - off);
         const uint64_t ibase = a.begin + off;
-        // the wave's next tile, which its chain tail runs into
-        const uint64_t off2 = (tile + wstride) * kTile;
-        const uint32_t tn2 = tile + wstride < a.ntiles ? (uint32_t)min((uint64_t)kTile, a.count - off2) : 0u;
+        const uint32_t tn2 = tile + 1 < t1 ? (uint32_t)min((uint64_t)kTile, a.count - off - kTile) : 0u;
 
         if constexpr (NARROW)
-            chain_tile_carry<kGenCarry>(stage, side_all[wv], tn, lane, (R)(2 * ibase + 1), tn2,
-                                        (R)(2 * (a.begin + off2) + 1),
-                                        [&](uint32_t r) { return hash_narrow(r, a.key); },
-                                        [](uint32_t r) { return r; }, cc);
+            chain_tile_next<kGenCarry>(stage, tn, tn2, lane, (R)(2 * ibase + 1),
+                                       [&](uint32_t r) { return hash_narrow(r, a.key); },
+                                       [](uint32_t r) { return r; }, cc, coff);
         else
-            chain_tile_carry<kGenCarry>(stage, side_all[wv], tn, lane, (R)(2 * ibase + 1), tn2,
-                                        (R)(2 * (a.begin + off2) + 1),
-                                        [&](uint64_t r) { return hash_wide(r, a.key); },
-                                        [&](uint64_t r) { return (uint32_t)div64(r >> 1, a.div); }, cc);
+            chain_tile_next<kGenCarry>(stage, tn, tn2, lane, (R)(2 * ibase + 1),
+                                       [&](uint64_t r) { return hash_wide(r, a.key); },
+                                       [&](uint64_t r) { return (uint32_t)div64(r >> 1, a.div); }, cc, coff);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
