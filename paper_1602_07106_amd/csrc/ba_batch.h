@@ -42,7 +42,7 @@ constexpr uint32_t kBatchTiles[3] = {1024, 2048, 4096};
 template <uint32_t TILE, uint32_t WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_gen_batch(BatchArgs a)
 {
-    __shared__ uint32_t stage_all[WAVES][TILE];
+    __shared__ uint32_t stage_all[WAVES][TILE + kGenCarry];  // a tile, then next-tile results of its tail
     const uint32_t lane = __lane_id();
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     uint32_t *stage = stage_all[wv];
@@ -57,6 +57,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_gen_batch(BatchArgs a)
     uint32_t j = lo;
     uint64_t tcur = a.tile0[j], tnext = a.tile0[j + 1];
     BatchInst I = a.inst[j];
+    // chains carried from a tile into the next tile of the same instance
+    // (none across instances: an instance's last tile claims nothing)
+    ChainCarry<uint32_t> c32;
+    ChainCarry<uint64_t> c64;
+    c32.li = c64.li = kIdle;
+    uint32_t coff = 0;
     for (uint64_t t = t0; t < t1; t++) {
         while (t >= tnext) {
             j++;
@@ -66,12 +72,15 @@ __global__ __launch_bounds__(WAVES * 64) void k_gen_batch(BatchArgs a)
         }
         const uint64_t off = (t - tcur) * TILE;
         const uint32_t tn = (uint32_t)min((uint64_t)TILE, I.m - off);
+        const uint32_t tn2 = t + 1 < t1 && t + 1 < tnext ? (uint32_t)min((uint64_t)TILE, I.m - off - TILE) : 0u;
         if (I.narrow)
-            chain_tile(stage, tn, lane, (uint32_t)(2 * off + 1), [&](uint32_t r) { return hash_narrow(r, I.key); },
-                       [](uint32_t r) { return r; });  // the final position; the flush divides
+            chain_tile_next<kGenCarry>(stage, tn, tn2, lane, (uint32_t)(2 * off + 1),
+                                       [&](uint32_t r) { return hash_narrow(r, I.key); },
+                                       [](uint32_t r) { return r; }, c32, coff);  // the final position; the flush divides
         else
-            chain_tile(stage, tn, lane, 2 * off + 1, [&](uint64_t r) { return hash_wide(r, I.key); },
-                       [&](uint64_t r) { return (uint32_t)div64(r >> 1, I.div); });
+            chain_tile_next<kGenCarry>(stage, tn, tn2, lane, 2 * off + 1,
+                                       [&](uint64_t r) { return hash_wide(r, I.key); },
+                                       [&](uint64_t r) { return (uint32_t)div64(r >> 1, I.div); }, c64, coff);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
