@@ -382,10 +382,12 @@ __device__ __forceinline__ void chain_tile_carry(uint32_t *stage, uint32_t *side
 // start position formula for both: the tail claims next-tile edges with the
 // steady loop's own refill, and costs one compare per step more than it
 // (the test whether a lane still holds an edge of this tile).  The next call
-// moves the early results (c.off on) to the front of its stage.
-template <uint32_t CAP, class R, class H, class O>
-__device__ __forceinline__ void chain_tile_next(uint32_t *stage, uint32_t tn, uint32_t tn2, uint32_t lane, R rbase,
-                                                H hash, O out, ChainCarry<R> &c, uint32_t &coff)
+// moves the early results (from coff on) to the front of its stage.  A chain
+// ends where stop(r) holds, as in chain_tile_until.
+template <uint32_t CAP, class R, class H, class S, class O>
+__device__ __forceinline__ void chain_tile_next_until(uint32_t *stage, uint32_t tn, uint32_t tn2, uint32_t lane,
+                                                      R rbase, H hash, S stop, O out, ChainCarry<R> &c,
+                                                      uint32_t &coff)
 {
     tn = wave_uniform(tn);
     const uint32_t ncl = wave_uniform(c.ncl);  // <= min(tn, CAP)
@@ -403,7 +405,7 @@ __device__ __forceinline__ void chain_tile_next(uint32_t *stage, uint32_t tn, ui
     uint32_t next = ncl + (uint32_t)__popcll(fm);  // next unclaimed index (wave-uniform)
     auto step = [&] {  // one step of every lane; refill from `next` (no lane may claim past lim)
         r = hash(r);
-        const bool fin = !((uint32_t)r & 1u);
+        const bool fin = stop(r);
         const uint64_t dm = __ballot(fin);
         if (fin) {
             *(lds_u32 *)(uintptr_t)sa = out(r);
@@ -424,7 +426,7 @@ __device__ __forceinline__ void chain_tile_next(uint32_t *stage, uint32_t tn, ui
     uint64_t live = __ballot(li < lim);
     while (cur) {
         r = hash(r);
-        const bool fin = !((uint32_t)r & 1u);
+        const bool fin = stop(r);
         const uint64_t dm = __ballot(fin) & live;
         if (fin && li < lim) {
             stage[li] = out(r);
@@ -439,6 +441,15 @@ __device__ __forceinline__ void chain_tile_next(uint32_t *stage, uint32_t tn, ui
     c.li = li < lim ? li - tn : kIdle;
     c.r = r;
     coff = tn;
+}
+
+// chain_tile_next of the plain model: chains end at the first even position.
+template <uint32_t CAP, class R, class H, class O>
+__device__ __forceinline__ void chain_tile_next(uint32_t *stage, uint32_t tn, uint32_t tn2, uint32_t lane, R rbase,
+                                                H hash, O out, ChainCarry<R> &c, uint32_t &coff)
+{
+    chain_tile_next_until<CAP>(stage, tn, tn2, lane, rbase, hash, [](R r) { return !((uint32_t)r & 1u); }, out, c,
+                               coff);
 }
 
 // One chain step for every lane, then refill of the lanes that finished.

@@ -120,20 +120,21 @@ struct ModelArgs {
 // so positions, bounds and the fmix high product stay 32-bit.
 // Block size: the CRC variants hold their tables in LDS per block (4 KiB
 // on 32-bit positions, 8 KiB on 64-bit), so they run 8 waves a block to
-// share them: 40 KiB blocks still fill a CU's 160 KiB at 8 waves per SIMD,
-// where 4-wave blocks of 24 KiB stop at 6.  The others run the generator's
-// 4 waves.
+// share them: 40 KiB blocks (stages with their tail room, and the tables)
+// still fill a CU's 160 KiB at 8 waves per SIMD on 32-bit positions, where
+// 4-wave blocks stop at 6.  The others run the generator's 4 waves.
 template <bool CRC>
 constexpr int kModelBlock = CRC ? 512 : kGenBlock;
 template <bool CRC>
 constexpr int kModelWaves = kModelBlock<CRC> / kWave;
+constexpr uint32_t kModelCarry = 128;  // next-tile edges a wave's chain tail may claim
 
 template <bool CRC, bool NOLOOPS, bool NARROW>
 __global__ __launch_bounds__(kModelBlock<CRC>) void k_gen_model(ModelArgs a)
 {
     constexpr int kBlock = kModelBlock<CRC>, kWaves = kModelWaves<CRC>;
     using R = typename std::conditional<NARROW, uint32_t, uint64_t>::type;
-    __shared__ uint32_t stage_all[kWaves][kTile];
+    __shared__ uint32_t stage_all[kWaves][kTile + kModelCarry];  // a tile, then next-tile results of its tail
     // CRC tables in LDS: all eight for 64-bit positions; with 32-bit
     // positions only the four of the low word's bytes (t[4..7])
     constexpr int kCrcRows = CRC ? (NARROW ? 4 : 8) : 1;
@@ -146,7 +147,14 @@ __global__ __launch_bounds__(kModelBlock<CRC>) void k_gen_model(ModelArgs a)
     const uint32_t lane = __lane_id();
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform: scalar loops
     uint32_t *stage = stage_all[wv];
-    const uint64_t wstride = (uint64_t)gridDim.x * kWaves;
+    // wave w takes tiles t0 .. t1-1, consecutive in edge IDs, so the chain
+    // tail of one tile runs straight into the next
+    const uint64_t nw = (uint64_t)gridDim.x * kWaves, w = (uint64_t)blockIdx.x * kWaves + wv;
+    const uint64_t per = a.ntiles / nw, extra = a.ntiles % nw;
+    const uint64_t t0 = w * per + min(w, extra), t1 = t0 + per + (w < extra ? 1u : 0u);
+    ChainCarry<R> cc;
+    cc.li = kIdle;
+    uint32_t coff = 0;
     const R P0 = (R)a.P0;
     const uint32_t stop_min = 0x80000000u - (uint32_t)(a.P0 >> 1);  // 32-bit positions only
     // 16-byte stores when the output is 16-byte aligned (tiles start at even edges)
@@ -204,12 +212,15 @@ __global__ __launch_bounds__(kModelBlock<CRC>) void k_gen_model(ModelArgs a)
         const uint64_t off = tile * kTile;
         const uint32_t tn = (uint32_t)min((uint64_t)kTile, a.count - off);
         const uint64_t ibase = a.begin + off;
+        const uint32_t tn2 = tile + 1 < t1 ? (uint32_t)min((uint64_t)kTile, a.count - off - kTile) : 0u;
         // 32-bit positions: the stage holds the final position r and the
         // flush maps it to its node, with every lane busy; 64-bit: the node.
         if constexpr (NARROW)
-            chain_tile_until(stage, tn, lane, (R)(a.P0 + 2 * ibase + 1), hash, stop, [](R r) { return r; });
+            chain_tile_next_until<kModelCarry>(stage, tn, tn2, lane, (R)(a.P0 + 2 * ibase + 1), hash, stop,
+                                               [](R r) { return r; }, cc, coff);
         else
-            chain_tile_until(stage, tn, lane, (R)(a.P0 + 2 * ibase + 1), hash, stop, node);
+            chain_tile_next_until<kModelCarry>(stage, tn, tn2, lane, (R)(a.P0 + 2 * ibase + 1), hash, stop, node,
+                                               cc, coff);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -250,7 +261,7 @@ __global__ __launch_bounds__(kModelBlock<CRC>) void k_gen_model(ModelArgs a)
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
 
-    for (uint64_t tile = (uint64_t)blockIdx.x * kWaves + wv; tile < a.ntiles; tile += wstride) {
+    for (uint64_t tile = t0; tile < t1; tile++) {
         if (a.div.pow2)
             run_tile(std::true_type{}, tile);
         else
