@@ -16,6 +16,12 @@
 // goes on to its next chunk without waiting for the block, and its chain
 // tail runs into the wave's tile of that chunk (chain_tile_carry).
 //
+// Chunks go to blocks round-robin (block b takes chunks b, b+P, ...), so
+// every block sees second endpoints from the whole edge range, as the region
+// capacities (sized for the mean) assume.  A block owning one contiguous
+// range would not: the targets of early edges all fall in the lowest
+// sub-buckets, whose regions then overflow into global atomics.
+//
 // Run length is what matters for the sort: a chunk's 22528 second endpoints
 // over 1024 sub-buckets leave runs of about 22 entries (44 bytes) per region
 // and chunk; shorter runs (smaller chunks, or 32768-node sub-buckets) cost
