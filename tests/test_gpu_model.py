@@ -58,6 +58,26 @@ def test_model_matches_the_oracle(no_loops, h, n0, m0, n, d, seed):
 
 
 @pytest.mark.parametrize("no_loops,h", FLAGS)
+def test_model_with_chain_tails_carried_across_tiles(no_loops, h):
+    # about 2 tiles per resident wave, so tile tails run into the next tile;
+    # whole graph, then a range that starts inside a tile
+    n0, m0, n, d, seed = 100, 1000, (1 << 20) + 333, 16, 5
+    _say("model carried tails", no_loops, h, n)
+    S, St = _seed_graph(n0, m0, seed + 200)
+    m = (n - n0) * d
+    # the oracle's sequential run lists the seed graph's m0 edges first
+    ref = oracle.model_bb_generate(n0, m0, S, n, d, seed, _oflags(no_loops, h)).reshape(-1)[2 * m0 :]
+    assert ref.size == 2 * m
+    out = ba.generate_model(n, d, seed, n0=n0, seed_edges=St, no_self_loops=no_loops, hash=h)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint32).reshape(-1), ref)
+    b, c = 4321, m // 2 + 17
+    out = ba.generate_model(n, d, seed, n0=n0, seed_edges=St, no_self_loops=no_loops, hash=h, begin=b, count=c)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint32).reshape(-1), ref[2 * b : 2 * (b + c)])
+
+
+@pytest.mark.parametrize("no_loops,h", FLAGS)
 def test_model_ranges_and_misaligned_outputs(no_loops, h):
     n0, m0, n, d, seed = 30, 45, 40000, 5, 11
     S, St = _seed_graph(n0, m0, 3)

@@ -75,6 +75,27 @@ def test_generate_without_degrees_and_misaligned_output():
         assert np.array_equal(_u32(view), E), shift
 
 
+def test_edges_only_with_chain_tails_carried_across_tiles():
+    # 2^26 edges: about 8 1024-edge tiles per resident wave, so nearly every
+    # tile's chain tail runs into the wave's next tile (and some tails hit
+    # the claim cap); whole graph at 16- and 4-byte alignment, then a range
+    # that starts inside a tile
+    n, d, seed = (1 << 20) + 777, 64, 5
+    m = n * d
+    _say("carried tails", n, d, seed)
+    E, _ = oracle.bb_generate(n, d, seed)
+    buf = torch.full((2 * m + 4,), -1, dtype=torch.int32, device="cuda")
+    for shift in [0, 1]:
+        view = buf[shift : shift + 2 * m]
+        ba.generate(n, d, seed, out=view)
+        torch.cuda.synchronize()
+        assert np.array_equal(_u32(view), E), shift
+    b, c = 12345, (1 << 24) + 99
+    out = ba.generate_range(n, d, seed, b, c)
+    torch.cuda.synchronize()
+    assert np.array_equal(_u32(out), E[2 * b : 2 * (b + c)])
+
+
 def test_ranges_stitch_to_the_whole_graph_and_accumulate_degrees():
     n, d, seed = 40000, 5, 77
     m = n * d
