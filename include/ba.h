@@ -297,7 +297,7 @@ int ba_batch_plan_rounds(uint32_t count, const uint64_t *n, const uint32_t *d, u
                          uint32_t *round_of, uint64_t *offset_of, uint32_t *rounds);
 
 /*
- * Served generation: continuous batching of requests on one stream.
+ * Served generation: continuous batching of requests.
  * A request is a plain BA graph (n, d, seed) and asks either for its whole
  * edge array (kind BA_REQ_EDGES: uint32 pairs as ba_generate writes them,
  * 8*n*d bytes) or for the streamed first-k degrees and edge checksum of
@@ -314,12 +314,16 @@ int ba_batch_plan_rounds(uint32_t count, const uint64_t *n, const uint32_t *d, u
  * finished steps and, when fewer than max_inflight steps are in flight,
  * launches one more: it admits queued requests in arrival order while their
  * outputs fit the free arena (admission by HBM bytes), runs every admitted
- * edge request as one batched persistent launch and every degree request
- * as a streaming launch, and records one event for the step (*launched =
- * requests admitted).  It never blocks on the GPU.  A request that cannot
- * fit even an empty arena is marked BA_JOB_FAILED.  If a launch of the step
- * fails, pump waits for the stream, marks the step's requests
- * BA_JOB_FAILED, frees their arena space and returns the error.
+ * edge request as one batched persistent launch on the caller's stream and
+ * the degree requests as batched streaming launches on a stream of the
+ * server's own (default priority, ordered after the step's table copy), so
+ * the two overlap, and records the step's events (*launched = requests
+ * admitted).  A step is complete when both streams have passed it; results
+ * are valid once their ticket is BA_JOB_READY, not in stream order.  It
+ * never blocks on the GPU.  A request that cannot fit even an empty arena
+ * is marked BA_JOB_FAILED.  If a launch of the step fails, pump waits for
+ * both streams, marks the step's requests BA_JOB_FAILED, frees their arena
+ * space and returns the error.
  * ba_server_poll reports a ticket's state and, once BA_JOB_READY, the GPU
  * completion time of its step in ms after the time origin and the byte
  * offset/size of its result in the arena.  ba_server_completed hands out
@@ -327,8 +331,8 @@ int ba_batch_plan_rounds(uint32_t count, const uint64_t *n, const uint32_t *d, u
  * call, oldest first, so a client need not poll every ticket.
  * ba_server_release returns a ready result's arena space (or drops a
  * failed request); a ticket is valid until it is released, and the
- * server's host memory follows the tickets still held.  ba_server_destroy waits for the stream and
- * frees the server (not the arena).  One host thread per server; calls on
+ * server's host memory follows the tickets still held.  ba_server_destroy
+ * waits for both streams and frees the server (not the arena).  One host thread per server; calls on
  * one server must not overlap.
  */
 enum { BA_REQ_EDGES = 0, BA_REQ_DEGREES = 1 };

@@ -1424,11 +1424,13 @@ int ba_server_create(void *arena, uint64_t arena_bytes, void *stream, ba_server 
     s->alloc = ArenaAlloc(s->arena_bytes);
     s->slot_bytes = batch_layout(kServerMaxBatch).bytes + stream_table_bytes(kServerMaxDeg);
     int rc = hip_check(hipHostMalloc((void **)&s->staging, s->slot_bytes * kServerSlots, hipHostMallocDefault));
+    if (!rc) rc = hip_check(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));  // default priority
     if (!rc) rc = hip_check(hipEventCreate(&s->start));
     if (!rc) rc = hip_check(hipEventRecord(s->start, s->stream));
     if (rc) {
         if (s->staging) (void)hipHostFree(s->staging);
         if (s->start) (void)hipEventDestroy(s->start);
+        if (s->side) (void)hipStreamDestroy(s->side);
         delete s;
         return rc;
     }
@@ -1441,9 +1443,12 @@ int ba_server_destroy(ba_server *s)
 {
     if (!s) return BA_EINVAL;
     int rc = hip_check(hipStreamSynchronize(s->stream));
-    for (auto &st : s->steps) (void)hipEventDestroy(st.ev);
+    const int rc2 = hip_check(hipStreamSynchronize(s->side));
+    if (!rc) rc = rc2;
+    for (auto &st : s->steps) server_step_events_free(st);
     if (s->start) (void)hipEventDestroy(s->start);
     if (s->staging) (void)hipHostFree(s->staging);
+    (void)hipStreamDestroy(s->side);
     delete s;
     return rc;
 }

@@ -83,7 +83,9 @@ struct ServerJob {
 };
 
 struct ServerStep {
-    hipEvent_t ev = nullptr;
+    hipEvent_t ev = nullptr;     // the caller's stream: table copy and edge batch done
+    hipEvent_t tab = nullptr;    // the caller's stream: table copy done (the degree stream waits for it)
+    hipEvent_t ev2 = nullptr;    // the degree stream: degree requests done (none without them)
     uint64_t table_off = 0, table_bytes = 0;  // the step's tables in the arena (edge batch, then degree requests)
     int slot = -1;  // pinned staging slot holding the tables, returned when the step retires
     ba_batch_info info{};         // the edge batch
@@ -111,7 +113,8 @@ static inline uint64_t stream_table_bytes(uint32_t njobs)
 struct ba_server {
     unsigned char *arena = nullptr;
     uint64_t arena_bytes = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // the caller's: tables and edge batches
+    hipStream_t side = nullptr;    // the server's own (default priority): degree requests
     hipEvent_t start = nullptr;
     ba::ArenaAlloc alloc{0};
     // jobs of tickets job_base .. job_base + jobs.size() - 1; released jobs
@@ -119,7 +122,7 @@ struct ba_server {
     std::deque<ba::ServerJob> jobs;
     uint64_t job_base = 0;
     std::deque<uint64_t> queue;
-    std::deque<ba::ServerStep> steps;  // in flight, oldest first (they finish in order on one stream)
+    std::deque<ba::ServerStep> steps;  // in flight, oldest first (retired in that order)
     std::vector<uint64_t> completed;   // tickets finished since the client last asked
     uint32_t inflight = 0;
     unsigned char *staging = nullptr;  // kServerSlots pinned table slots
@@ -149,8 +152,17 @@ static uint64_t job_output_bytes(const ba_request &r, uint64_t m)
     return r.kind == BA_REQ_EDGES ? 8 * m : 8 * (r.first_k + 1);  // degrees: first_k counts + checksum
 }
 
+static void server_step_events_free(ServerStep &st)
+{
+    for (hipEvent_t *e : {&st.ev, &st.tab, &st.ev2}) {
+        if (*e) (void)hipEventDestroy(*e);
+        *e = nullptr;
+    }
+}
+
 // Retire finished steps (non-blocking): mark their jobs ready with the GPU
-// completion time and free their tables.  Steps finish in launch order.
+// completion time and free their tables, oldest first; a step is finished
+// when both streams have passed its events.
 static int server_retire(ba_server *s)
 {
     while (!s->steps.empty()) {
@@ -159,8 +171,15 @@ static int server_retire(ba_server *s)
         if (q == hipErrorNotReady) break;
         int rc = hip_check(q);
         if (rc) return rc;
-        float ms = 0.0f;
+        if (st.ev2) {
+            const hipError_t q2 = hipEventQuery(st.ev2);
+            if (q2 == hipErrorNotReady) break;
+            if ((rc = hip_check(q2))) return rc;
+        }
+        float ms = 0.0f, ms2 = 0.0f;
         if ((rc = hip_check(hipEventElapsedTime(&ms, s->start, st.ev)))) return rc;
+        if (st.ev2 && (rc = hip_check(hipEventElapsedTime(&ms2, s->start, st.ev2)))) return rc;
+        ms = std::max(ms, ms2);  // the step ends with the later of its two streams
         for (uint64_t j : st.jobs) {
             ServerJob *J = server_job(s, j);
             J->state = BA_JOB_READY;
@@ -170,7 +189,7 @@ static int server_retire(ba_server *s)
         if (st.table_bytes) s->alloc.release(st.table_off, st.table_bytes);
         if (st.slot >= 0) s->free_slots.push_back(st.slot);
         st.slot = -1;
-        (void)hipEventDestroy(st.ev);
+        server_step_events_free(st);
         s->steps.pop_front();
         s->inflight--;
     }
@@ -286,9 +305,10 @@ static int server_launch_step(ba_server *s, uint32_t *launched)
     const BatchLayout L = batch_layout(ne);
     const uint64_t eb_bytes = ne ? L.bytes : 0, sb_bytes = nd ? stream_table_bytes(nd) : 0;
     // A launch of the step failed: part of it may already be queued, so wait
-    // for the stream, then fail the step's requests and free what they held.
+    // for both streams, then fail the step's requests and free what they held.
     auto fail_step = [&](int err) {
         (void)hipStreamSynchronize(s->stream);
+        (void)hipStreamSynchronize(s->side);
         for (const auto *list : {&edge_jobs, &deg_jobs}) {
             for (uint64_t j : *list) {
                 ServerJob &J = *server_job(s, j);
@@ -299,7 +319,7 @@ static int server_launch_step(ba_server *s, uint32_t *launched)
         }
         if (st.table_bytes) s->alloc.release(st.table_off, st.table_bytes);
         if (st.slot >= 0) s->free_slots.push_back(st.slot);
-        if (st.ev) (void)hipEventDestroy(st.ev);
+        server_step_events_free(st);
         *launched = 0;
         return err;
     };
@@ -353,6 +373,14 @@ static int server_launch_step(ba_server *s, uint32_t *launched)
                                            s->stream));
         if (rc2) return fail_step(rc2);
     }
+    // The degree requests run on the server's own stream, after the table
+    // copy, beside the edge batch: each launch's tail then overlaps the other.
+    const bool degs = nd || !deg_single.empty();
+    if (degs) {
+        if ((rc = hip_check(hipEventCreateWithFlags(&st.tab, hipEventDisableTiming)))) return fail_step(rc);
+        if ((rc = hip_check(hipEventRecord(st.tab, s->stream)))) return fail_step(rc);
+        if ((rc = hip_check(hipStreamWaitEvent(s->side, st.tab, 0)))) return fail_step(rc);
+    }
     if (ne) {
         if ((rc = ba_batch_launch(&st.info, s->arena + st.table_off, (uint32_t *)s->arena, s->arena_bytes / 4,
                                   s->stream)))
@@ -365,8 +393,8 @@ static int server_launch_step(ba_server *s, uint32_t *launched)
         a.base = (uint64_t *)s->arena;
         a.jobs = SJ;
         a.njobs = nd;
-        if ((rc = launch_timed(BA_KT_OTHER, s->stream, [&] {
-                 hipLaunchKernelGGL(k_stream_batch_init, dim3(std::min<uint32_t>(nd, 1024)), dim3(256), 0, s->stream,
+        if ((rc = launch_timed(BA_KT_OTHER, s->side, [&] {
+                 hipLaunchKernelGGL(k_stream_batch_init, dim3(std::min<uint32_t>(nd, 1024)), dim3(256), 0, s->side,
                                     a);
              })))
             return fail_step(rc);
@@ -378,11 +406,11 @@ static int server_launch_step(ba_server *s, uint32_t *launched)
             a.units = (uint32_t)st.units[tier];
             a.next = next + tier;
             const uint32_t grid = (uint32_t)std::min<uint64_t>(tier ? g64 : g16, st.units[tier]);
-            if ((rc = launch_timed(BA_KT_STREAM, s->stream, [&] {
+            if ((rc = launch_timed(BA_KT_STREAM, s->side, [&] {
                      if (tier)
-                         hipLaunchKernelGGL(k_stream_batch<true>, dim3(grid), dim3(kStreamBlock), 0, s->stream, a);
+                         hipLaunchKernelGGL(k_stream_batch<true>, dim3(grid), dim3(kStreamBlock), 0, s->side, a);
                      else
-                         hipLaunchKernelGGL(k_stream_batch<false>, dim3(grid), dim3(kStreamBlock), 0, s->stream, a);
+                         hipLaunchKernelGGL(k_stream_batch<false>, dim3(grid), dim3(kStreamBlock), 0, s->side, a);
                  })))
                 return fail_step(rc);
         }
@@ -390,11 +418,15 @@ static int server_launch_step(ba_server *s, uint32_t *launched)
     for (uint64_t j : deg_single) {
         const ServerJob &J = *server_job(s, j);
         uint64_t *deg = (uint64_t *)(s->arena + J.out_off);
-        if ((rc = ba_degrees(J.req.n, J.req.d, J.req.seed, J.req.first_k, deg, deg + J.req.first_k, s->stream)))
+        if ((rc = ba_degrees(J.req.n, J.req.d, J.req.seed, J.req.first_k, deg, deg + J.req.first_k, s->side)))
             return fail_step(rc);
     }
     if ((rc = hip_check(hipEventCreate(&st.ev)))) return fail_step(rc);
     if ((rc = hip_check(hipEventRecord(st.ev, s->stream)))) return fail_step(rc);
+    if (degs) {
+        if ((rc = hip_check(hipEventCreate(&st.ev2)))) return fail_step(rc);
+        if ((rc = hip_check(hipEventRecord(st.ev2, s->side)))) return fail_step(rc);
+    }
     for (uint64_t j : edge_jobs) st.jobs.push_back(j);
     for (uint64_t j : deg_jobs) st.jobs.push_back(j);
     for (uint64_t j : st.jobs) server_job(s, j)->state = BA_JOB_RUNNING;
