@@ -339,7 +339,7 @@ def served_line(args) -> dict:
                 t = srv.submit_degrees(int(tr["n"][i]), int(tr["d"][i]), int(tr["seed"][i]), int(tr["first_k"][i]))
             ticket_of[t] = i
             i += 1
-        admitted = srv.pump(max_inflight=2)
+        admitted = srv.pump(max_inflight=args.served_inflight)
         fin = srv.completed()
         for t in fin:
             st, ms, _, _ = srv.poll(t)
@@ -374,6 +374,7 @@ def served_line(args) -> dict:
         "max_ms": float(lat.max()),
         "arrival_span_s": float(arrival[-1]),
         "makespan_s": makespan,
+        "inflight_steps": args.served_inflight,
         "served_edges_per_s": total / makespan,
         "offered_edges_per_s": total / float(arrival[-1]),
     }
@@ -606,6 +607,8 @@ def main() -> int:
                          "stream: streamed first-10^5 degrees at n=2^30, d=64; "
                          "model: the generalized model (seed graph, no-self-loop draws, CRC hash); "
                          "rates: VALU issue-rate and 16-byte fill microbenchmarks (the ALU roofline's prices)")
+    ap.add_argument("--served-inflight", type=int, default=2, metavar="STEPS",
+                    help="steps the served workload keeps in flight (server pump's max_inflight)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="graph workload only: skip the batched and served parts of the metric")
