@@ -464,9 +464,10 @@ class Request(ctypes.Structure):
 
 
 class Server:
-    """Continuous batching of generation requests on one stream (see
-    ba_server_* in include/ba.h).  Results live in a device arena of
-    arena_bytes until released."""
+    """Continuous batching of generation requests (see ba_server_* in
+    include/ba.h): edge batches on `stream`, degree batches on a stream of
+    the server's own.  Results live in a device arena of arena_bytes until
+    released, and are valid once their ticket is ready."""
 
     def __init__(self, arena_bytes: int, device=None, stream: Optional[torch.cuda.Stream] = None):
         dev = _device(device)

@@ -6,12 +6,13 @@
 // bytes); a request that does not fit is passed over, not waited for, until
 // it has been passed over kServerMaxBypass steps in a row, after which
 // nothing behind it is admitted until it fits.  All admitted edge-list
-// requests run as ONE batched persistent launch, all admitted degree
-// requests as one batched streaming launch per LDS tier (their tables go to
-// the arena from pinned staging), and the step records one event.  Steps
-// queue on the server's stream, so the host admits the next batch while
-// earlier ones run; results stay in the arena (device-resident) until the
-// client releases them.
+// requests run as ONE batched persistent launch on the caller's stream, all
+// admitted degree requests as one batched streaming launch per LDS tier on
+// the server's own stream, which follows the step's table copy (the tables
+// go to the arena from pinned staging), so the two kinds overlap.  Steps
+// queue on the two streams, so the host admits the next batch while earlier
+// ones run; a step retires once both streams have passed it, and results
+// stay in the arena (device-resident) until the client releases them.
 //
 // The paper hands batches of edge IDs to processors as they become free
 // (Section 2, last paragraph); here whole requests are the units and the
