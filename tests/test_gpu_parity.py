@@ -96,6 +96,31 @@ def test_edges_only_with_chain_tails_carried_across_tiles():
     assert np.array_equal(_u32(out), E[2 * b : 2 * (b + c)])
 
 
+def test_random_sweep_of_ranges_with_carried_tails():
+    # seeded random graphs and ranges of 1e7..4e7 edges (more tiles than
+    # resident waves in both generators), d with and without a power of two,
+    # ranges starting inside a tile; every other case with degrees (the fused
+    # kernel on a range, both endpoints added)
+    rng = np.random.default_rng(20261203)
+    for k in range(8):
+        d = int(rng.choice([1, 2, 3, 5, 7, 12, 16, 31, 33, 64]))
+        n = max(2, int(rng.integers(10_000_000, 40_000_000)) // d + int(rng.integers(0, 1000)))
+        m = n * d
+        b = int(rng.integers(0, m // 4))
+        c = int(rng.integers(m // 2, m - b))
+        seed = int(rng.integers(0, 1 << 63))
+        with_deg = k % 2 == 1
+        _say("sweep", k, n, d, seed, b, c, with_deg)
+        deg = torch.zeros(n, dtype=torch.int32, device="cuda") if with_deg else None
+        out = ba.generate_range(n, d, seed, b, c, deg=deg)
+        torch.cuda.synchronize()
+        ref, _ = oracle.edges_range(d, seed, b, c)
+        ref = ref.astype(np.uint32)
+        assert np.array_equal(_u32(out), ref), k
+        if with_deg:
+            assert np.array_equal(_u32(deg).astype(np.int64), np.bincount(ref, minlength=n)), k
+
+
 def test_ranges_stitch_to_the_whole_graph_and_accumulate_degrees():
     n, d, seed = 40000, 5, 77
     m = n * d
