@@ -240,59 +240,6 @@ __device__ __forceinline__ void chain_run_visit(uint32_t tn, uint32_t lane, R rb
 
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
-// The chain loop writing out(r) of edge li to stage[li].  The same refill
-// as chain_tile_visit, but a lane keeps the LDS byte address of its stage
-// slot instead of li: a finishing lane's next slot and restart position are
-// each one multiply-add of its rank onto a wave-uniform base (the slot and
-// position of edge `next`), where going through li costs more instructions
-// on every step.
-template <class R, class H, class S, class O>
-__device__ __forceinline__ void chain_tile_until(uint32_t *stage, uint32_t tn, uint32_t lane, R rbase, H hash,
-                                                 S stop, O out)
-{
-    tn = __builtin_amdgcn_readfirstlane(tn);  // wave-uniform: keeps loop control scalar
-    const uint32_t sbase = wave_uniform((uint32_t)(uintptr_t)(lds_u32 *)stage);  // LDS byte address
-    uint32_t sa = sbase + 4 * lane;
-    uint32_t next = kWave;  // next unclaimed edge (wave-uniform)
-    R r = rbase + 2 * (R)lane;
-    if (tn >= kWave) {
-        while (next + kWave <= tn) {
-            r = hash(r);
-            const bool fin = stop(r);
-            const uint64_t dm = __ballot(fin);
-            if (fin) {
-                *(lds_u32 *)(uintptr_t)sa = out(r);
-                const uint32_t k = lane_rank(dm);
-                sa = wave_uniform(sbase + 4 * next) + 4 * k;
-                r = wave_uniform((R)(rbase + 2 * (R)next)) + 2 * (R)k;
-            }
-            next += (uint32_t)__popcll(dm);
-        }
-    }
-    // tail, as in chain_tile_visit: live iff li < tn
-    uint32_t li = (sa - sbase) >> 2;
-    uint64_t live = __ballot(li < tn);
-    while (live) {
-        r = hash(r);
-        const bool fin = stop(r);
-        const uint64_t dm = __ballot(fin) & live;
-        if (fin && li < tn) {
-            stage[li] = out(r);
-            li = next + lane_rank(dm);
-            r = rbase + 2 * (R)li;
-        }
-        next += (uint32_t)__popcll(dm);
-        live = __ballot(li < tn);
-    }
-}
-
-// The plain model: chains end at the first even position.
-template <class R, class H, class O>
-__device__ __forceinline__ void chain_tile(uint32_t *stage, uint32_t tn, uint32_t lane, R rbase, H hash, O out)
-{
-    chain_tile_until(stage, tn, lane, rbase, hash, [](R r) { return !((uint32_t)r & 1u); }, out);
-}
-
 // Chain-loop state a wave carries from one of its tiles into its next
 // (chain_tile_carry): the next tile's first ncl edges are claimed; a lane
 // still running one of them keeps its position and its index there, and
@@ -305,15 +252,20 @@ struct ChainCarry {
     uint32_t ncl = 0;  // wave-uniform: edges of the next tile claimed (a prefix)
 };
 
-// chain_tile of the plain model with the tail filled from the wave's next
-// tile (tn2 edges from position rbase2; none if tn2 = 0).  Once every edge
-// of this tile is claimed, a finishing lane takes the next unclaimed edge of
-// the next tile, at most CAP of them, instead of idling while the tile's
-// last chains run; a finished next-tile edge stores its result at
-// side[index].  The call for the next tile, with the same carry, copies
-// those into its stage and resumes the chains still running.  Every edge's
-// result lands at the same stage slot as with chain_tile, so the order in
-// which chains run changes nothing downstream.
+// The chain loop of one tile of tn edges of the plain model (chains end at
+// the first even position), writing out(r) of edge li to stage[li], with
+// the tail filled from the wave's next tile (tn2 edges from position
+// rbase2; none if tn2 = 0).  The refill is chain_tile_visit's, but a lane
+// keeps the LDS byte address of its stage slot instead of li: a finishing
+// lane's next slot and restart position are each one multiply-add of its
+// rank onto a wave-uniform base (the slot and position of edge `next`).
+// Once every edge of this tile is claimed, a finishing lane takes the next
+// unclaimed edge of the next tile, at most CAP of them, instead of idling
+// while the tile's last chains run; a finished next-tile edge stores its
+// result at side[index].  The call for the next tile, with the same carry,
+// copies those into its stage and resumes the chains still running.  Every
+// edge's result lands at the same stage slot whatever order its chain runs
+// in, so nothing downstream changes.
 template <uint32_t CAP, class R, class H, class O>
 __device__ __forceinline__ void chain_tile_carry(uint32_t *stage, uint32_t *side, uint32_t tn, uint32_t lane,
                                                  R rbase, uint32_t tn2, R rbase2, H hash, O out, ChainCarry<R> &c)
@@ -337,7 +289,7 @@ __device__ __forceinline__ void chain_tile_carry(uint32_t *stage, uint32_t *side
     }
     uint32_t next = ncl + (uint32_t)__popcll(fm);  // next unclaimed index (wave-uniform)
     if (next + kWave <= tn) {
-        // every lane's edge is in this tile (li < next): the steady loop of chain_tile_until
+        // every lane's edge is in this tile (li < next): the steady loop
         uint32_t sa = sbase + 4 * li;
         do {
             r = hash(r);
@@ -383,7 +335,8 @@ __device__ __forceinline__ void chain_tile_carry(uint32_t *stage, uint32_t *side
 // steady loop's own refill, and costs one compare per step more than it
 // (the test whether a lane still holds an edge of this tile).  The next call
 // moves the early results (from coff on) to the front of its stage.  A chain
-// ends where stop(r) holds, as in chain_tile_until.
+// ends where stop(r) holds: an even position, or a seed-graph position in
+// the generalized model.
 template <uint32_t CAP, class R, class H, class S, class O>
 __device__ __forceinline__ void chain_tile_next_until(uint32_t *stage, uint32_t tn, uint32_t tn2, uint32_t lane,
                                                       R rbase, H hash, S stop, O out, ChainCarry<R> &c,
