@@ -1,7 +1,9 @@
 """ba_generate_static (the whole graph and its degrees with the degree
 pipeline's workspace in the library's static device scratch, no allocation)
 against ba_generate_ws with a caller workspace: bit-exact, on two calls in a
-row, the second with a smaller graph, and without any device allocation."""
+row, the second with a smaller graph, and without any device allocation;
+then captured into a HIP graph and replayed, with eager calls on the same
+scratch between the replays."""
 import ctypes
 import sys
 
@@ -102,3 +104,45 @@ def test_static_without_degrees_and_refusals():
     assert L.ba_generate_static(1 << 28, 1, 0, small.data_ptr(), small.data_ptr(), st) == ba.BA_ENOMEM
     torch.cuda.synchronize()
     assert int((small != 7).sum()) == 0
+
+
+def test_static_entry_point_replays_from_a_captured_graph():
+    L = ba.lib()
+    # 2^28 edges: the degree pipeline needs several passes through the
+    # 256 MiB scratch, so the graph holds every pass's launches
+    n, d, seed = (1 << 24) + 77, 16, 13
+    m = n * d
+    _say("static graph capture", n, d, seed)
+    ref_e = torch.empty(2 * m, dtype=torch.int32, device="cuda")
+    ref_d = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = ba.workspace(n, d, m)
+    st = torch.cuda.current_stream().cuda_stream
+    assert L.ba_generate_ws(n, d, seed, ref_e.data_ptr(), ref_d.data_ptr(), ws.data_ptr(), ws.numel(), st) == 0
+    torch.cuda.synchronize()
+    del ws
+    edges = torch.full((2 * m,), -1, dtype=torch.int32, device="cuda")
+    deg = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    # an eager call first: the scratch's address is looked up once per device
+    assert L.ba_generate_static(n, d, seed, edges.data_ptr(), deg.data_ptr(), st) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(edges, ref_e) and torch.equal(deg, ref_d)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rc = L.ba_generate_static(n, d, seed, edges.data_ptr(), deg.data_ptr(),
+                                  torch.cuda.current_stream().cuda_stream)
+    assert rc == 0
+    other_e = torch.empty(2 * 99991 * 7, dtype=torch.int32, device="cuda")
+    other_d = torch.empty(99991, dtype=torch.int32, device="cuda")
+    for rep in range(3):
+        _say("replay", rep)
+        edges.fill_(-1)
+        deg.fill_(-1)
+        # eager work on the same scratch between replays
+        assert L.ba_generate_static(99991, 7, rep, other_e.data_ptr(), other_d.data_ptr(),
+                                    torch.cuda.current_stream().cuda_stream) == 0
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(edges, ref_e), rep
+        assert torch.equal(deg, ref_d), rep
+    del g
