@@ -247,9 +247,9 @@ typedef __attribute__((address_space(3))) uint32_t lds_u32;
 constexpr uint32_t kIdle = 0xFFFFFFFFu;
 template <class R>
 struct ChainCarry {
-    R r;               // per lane: the chain's current position (valid iff li < ncl)
-    uint32_t li;       // per lane: index of its edge in the next tile, or kIdle
-    uint32_t ncl = 0;  // wave-uniform: edges of the next tile claimed (a prefix)
+    R r = 0;             // per lane: the chain's current position (valid iff li < ncl)
+    uint32_t li = kIdle; // per lane: index of its edge in the next tile, or kIdle
+    uint32_t ncl = 0;    // wave-uniform: edges of the next tile claimed (a prefix)
 };
 
 // The chain loop of one tile of tn edges of the plain model (chains end at
@@ -424,7 +424,6 @@ __global__ __launch_bounds__(kGenBlock) void k_gen_u32(GenArgs a)
     const uint64_t t0 = w * per + min(w, extra), t1 = t0 + per + (w < extra ? 1u : 0u);
     using R = std::conditional_t<NARROW, uint32_t, uint64_t>;
     ChainCarry<R> cc;
-    cc.li = kIdle;
     uint32_t coff = 0;
 
     for (uint64_t tile = t0; tile < t1; tile++) {

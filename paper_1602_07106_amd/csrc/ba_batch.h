@@ -61,7 +61,6 @@ __global__ __launch_bounds__(WAVES * 64) void k_gen_batch(BatchArgs a)
     // (none across instances: an instance's last tile claims nothing)
     ChainCarry<uint32_t> c32;
     ChainCarry<uint64_t> c64;
-    c32.li = c64.li = kIdle;
     uint32_t coff = 0;
     for (uint64_t t = t0; t < t1; t++) {
         while (t >= tnext) {

@@ -76,7 +76,6 @@ __global__ __launch_bounds__(kFBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
     uint32_t *side_w = side_all[wv];
     using R = std::conditional_t<NARROW, uint32_t, uint64_t>;
     ChainCarry<R> cc;
-    cc.li = kIdle;
     // this wave's tile of chunk ch: first edge offset and size
     auto tile_of = [&](uint64_t ch, uint64_t &woff) -> uint32_t {
         woff = ch * kFChunk + (uint64_t)wv * kFTile;

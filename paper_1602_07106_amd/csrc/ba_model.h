@@ -153,7 +153,6 @@ __global__ __launch_bounds__(kModelBlock<CRC>) void k_gen_model(ModelArgs a)
     const uint64_t per = a.ntiles / nw, extra = a.ntiles % nw;
     const uint64_t t0 = w * per + min(w, extra), t1 = t0 + per + (w < extra ? 1u : 0u);
     ChainCarry<R> cc;
-    cc.li = kIdle;
     uint32_t coff = 0;
     const R P0 = (R)a.P0;
     const uint32_t stop_min = 0x80000000u - (uint32_t)(a.P0 >> 1);  // 32-bit positions only
