@@ -455,50 +455,100 @@ __device__ __forceinline__ bool hist_part(const DegArgs &a, uint32_t k, HistPart
 // Calls f(x) for every entry x (a 16-bit local index) of the regions the
 // calling wave takes of a part: regions p0 + wv, p0 + wv + 16, ...  Lane j
 // fetches the fill of the wave's j-th region up front (at most kPBlocksMax /
-// 16 = 64 regions a wave), so no region waits on a load of its own length;
-// 8 entries per 16-byte load where aligned, four loads in flight per lane
-// before their entries are visited.  Returns the wave's entry count.
+// 16 = 64 regions a wave), so no region waits on a load of its own length.
+// A region is read in batches of up to four 16-byte loads per lane (8
+// entries each, where aligned); its first batch also carries the unaligned
+// head and the tail, one element per lane (each is shorter than 8 entries).
+// The loads of the next batch, of this region or the next, are issued
+// before the current batch's entries are visited, so the reads and the
+// counting overlap.  Returns the wave's entry count.
 template <class F>
 __device__ __forceinline__ uint32_t hist_visit(const DegArgs &a, const HistPart &h, F f)
 {
-    static_assert(kPBlocksMax / (kHBlock / 64) <= 64, "one region fill per lane");
+    constexpr uint32_t kHW = kHBlock / 64;  // waves of the block: a wave takes every kHW-th region
+    static_assert(kPBlocksMax / kHW <= 64, "one region fill per lane");
     const uint32_t N = a.p.NBsub, g = h.g;
     const uint32_t cp = ws_rcap(a)[g];
     const uint64_t base = ws_off(a)[g];
     const uint32_t *fill = ws_fill(a);
     const uint16_t *L = ws_L(a);
     const uint32_t lane = __lane_id(), wv = threadIdx.x / 64;
-    const uint32_t pl = h.p0 + wv + (kHBlock / 64) * lane;
+    const uint32_t p00 = h.p0 + wv;
+    const uint32_t pl = p00 + kHW * lane;
     const uint32_t nl = pl < h.p1 ? min(fill[(uint64_t)pl * N + g], cp) : 0u;
-    uint32_t total = 0;
-    for (uint32_t p = h.p0 + wv, jr = 0; p < h.p1; p += kHBlock / 64, jr++) {
-        const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)nl, (int)jr);  // jr is wave-uniform
-        total += n;
-        const uint16_t *src = L + base + (uint64_t)p * cp;
-        const uint32_t head = min(n, (uint32_t)((8 - (((uintptr_t)src >> 1) & 7)) & 7));
-        if (lane < head) f((uint32_t)src[lane]);
-        const uint32_t nv = (n - head) / 8;
-        const uint4 *vs = reinterpret_cast<const uint4 *>(src + head);
-        auto visit8 = [&](const uint4 &q) {
-            f(q.x & 0xFFFFu);
-            f(q.x >> 16);
-            f(q.y & 0xFFFFu);
-            f(q.y >> 16);
-            f(q.z & 0xFFFFu);
-            f(q.z >> 16);
-            f(q.w & 0xFFFFu);
-            f(q.w >> 16);
-        };
-        uint32_t t = lane;
-        for (; t + 192 < nv; t += 256) {
-            const uint4 q0 = vs[t], q1 = vs[t + 64], q2 = vs[t + 128], q3 = vs[t + 192];
-            visit8(q0);
-            visit8(q1);
-            visit8(q2);
-            visit8(q3);
+    const uint32_t nreg = p00 < h.p1 ? (h.p1 - p00 + kHW - 1) / kHW : 0u;  // the wave's regions
+    if (nreg == 0) return 0;
+    struct Region {
+        const uint16_t *src;
+        uint32_t n, head, nv;  // entries, unaligned head, whole 16-byte vectors after it
+    };
+    struct Batch {
+        uint4 q[4];
+        uint32_t hv, tv;  // first batch: a head and a tail element
+    };
+    auto region = [&](uint32_t jr) {
+        Region R;
+        R.n = (uint32_t)__builtin_amdgcn_readlane((int)nl, (int)jr);  // jr is wave-uniform
+        R.src = L + base + (uint64_t)(p00 + kHW * jr) * cp;
+        R.head = min(R.n, (uint32_t)((8 - (((uintptr_t)R.src >> 1) & 7)) & 7));
+        R.nv = (R.n - R.head) / 8;
+        return R;
+    };
+    auto load = [&](Batch &B, const Region &R, uint32_t b) {
+        const uint4 *vs = reinterpret_cast<const uint4 *>(R.src + R.head);
+#pragma unroll
+        for (uint32_t k = 0; k < 4; k++) {
+            const uint32_t t = lane + 64 * (4 * b + k);
+            B.q[k] = t < R.nv ? vs[t] : make_uint4(0u, 0u, 0u, 0u);
         }
-        for (; t < nv; t += 64) visit8(vs[t]);
-        for (uint32_t x = head + nv * 8 + lane; x < n; x += 64) f((uint32_t)src[x]);
+        if (b == 0) {
+            const uint32_t x = R.head + R.nv * 8 + lane;
+            B.hv = lane < R.head ? (uint32_t)R.src[lane] : 0u;
+            B.tv = x < R.n ? (uint32_t)R.src[x] : 0u;
+        }
+    };
+    auto visit8 = [&](const uint4 &q) {
+        f(q.x & 0xFFFFu);
+        f(q.x >> 16);
+        f(q.y & 0xFFFFu);
+        f(q.y >> 16);
+        f(q.z & 0xFFFFu);
+        f(q.z >> 16);
+        f(q.w & 0xFFFFu);
+        f(q.w >> 16);
+    };
+    auto visit = [&](const Batch &B, const Region &R, uint32_t b) {
+#pragma unroll
+        for (uint32_t k = 0; k < 4; k++)
+            if (lane + 64 * (4 * b + k) < R.nv) visit8(B.q[k]);
+        if (b == 0) {
+            if (lane < R.head) f(B.hv);
+            if (R.head + R.nv * 8 + lane < R.n) f(B.tv);
+        }
+    };
+    Region cur = region(0);
+    uint32_t total = cur.n, jr = 0, b = 0;
+    Batch bc, bn;
+    load(bc, cur, 0);
+    for (;;) {
+        // the batch after (jr, b): the region's next one, else the next region's first
+        const uint32_t nb = cur.nv > 256 ? (cur.nv + 255) / 256 : 1u;
+        Region nxt = cur;
+        uint32_t jr2 = jr, b2 = b + 1;
+        if (b2 == nb) {
+            jr2 = jr + 1;
+            b2 = 0;
+            if (jr2 < nreg) nxt = region(jr2);
+        }
+        const bool more = jr2 < nreg;
+        if (more) load(bn, nxt, b2);
+        visit(bc, cur, b);
+        if (!more) break;
+        if (b2 == 0) total += nxt.n;
+        cur = nxt;
+        jr = jr2;
+        b = b2;
+        bc = bn;
     }
     return total;
 }
