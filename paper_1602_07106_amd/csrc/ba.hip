@@ -118,6 +118,21 @@ __device__ __forceinline__ void flush_pair(const GenArgs &a, const uint32_t *sta
     }
 }
 
+// Edge-pair output is written once and never read back by the kernel that
+// writes it, so its stores are non-temporal: they stream through L2 instead
+// of taking its lines from data that is still being assembled there (the
+// fused generator's partially written partition regions, which then reach
+// HBM in pieces).
+__device__ __forceinline__ void store_nt(uint32_t *p, uint32_t x) { __builtin_nontemporal_store(x, p); }
+
+// (u0, v0, u1, v1) to a 16-byte aligned p.
+__device__ __forceinline__ void store_edges16(uint32_t *p, uint32_t u0, uint32_t v0, uint32_t u1, uint32_t v1)
+{
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 x = {u0, v0, u1, v1};
+    __builtin_nontemporal_store(x, reinterpret_cast<u32x4 *>(p));
+}
+
 // Edges j and j+1 (when j+1 < tn) to the output, one 16-byte store when aligned.
 template <bool VEC16>
 __device__ __forceinline__ void store_pair(uint32_t *out, uint32_t j, uint32_t tn, uint32_t u0, uint32_t v0,
@@ -125,13 +140,13 @@ __device__ __forceinline__ void store_pair(uint32_t *out, uint32_t j, uint32_t t
 {
     const bool two = j + 1 < tn;
     if (VEC16 && two) {
-        *reinterpret_cast<uint4 *>(out + 2 * j) = make_uint4(u0, v0, u1, v1);
+        store_edges16(out + 2 * j, u0, v0, u1, v1);
     } else {
-        out[2 * j] = u0;
-        out[2 * j + 1] = v0;
+        store_nt(out + 2 * j, u0);
+        store_nt(out + 2 * j + 1, v0);
         if (two) {
-            out[2 * j + 2] = u1;
-            out[2 * j + 3] = v1;
+            store_nt(out + 2 * j + 2, u1);
+            store_nt(out + 2 * j + 3, v1);
         }
     }
 }
@@ -459,7 +474,7 @@ __global__ __launch_bounds__(kGenBlock) void k_gen_u32(GenArgs a)
                     uint32_t u0, u1, v0, v1;
                     flush_pair<NARROW, P>(a, stage, ibase, j, u0, u1, v0, v1);
                     if constexpr (VEC16)
-                        *reinterpret_cast<uint4 *>(out + 2 * j) = make_uint4(u0, v0, u1, v1);
+                        store_edges16(out + 2 * j, u0, v0, u1, v1);
                     else
                         store_pair<false>(out, j, kTile, u0, v0, u1, v1);
                     if constexpr (DM == kDegList) *reinterpret_cast<uint2 *>(a.vlist + off + j) = make_uint2(v0, v1);

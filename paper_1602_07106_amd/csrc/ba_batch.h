@@ -115,7 +115,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_gen_batch(BatchArgs a)
                     const uint32_t jj = 2 * lane + t * (2 * kWave);
                     uint32_t u0, u1, v0, v1;
                     pair(jj, u0, u1, v0, v1);
-                    *reinterpret_cast<uint4 *>(out + 2 * jj) = make_uint4(u0, v0, u1, v1);
+                    store_edges16(out + 2 * jj, u0, v0, u1, v1);
                 }
             } else {
                 for (uint32_t jj = 2 * lane; jj < tn; jj += 2 * kWave) {

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kFBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
                     uint32_t u0, u1, v0, v1;
                     flush_pair<NARROW, POW2>(a.g, st_w, ibase, j, u0, u1, v0, v1);
                     if constexpr (VEC16)
-                        *reinterpret_cast<uint4 *>(out + 2 * j) = make_uint4(u0, v0, u1, v1);
+                        store_edges16(out + 2 * j, u0, v0, u1, v1);
                     else
                         store_pair<false>(out, j, kFTile, u0, v0, u1, v1);
                     v[2 * t] = v0;

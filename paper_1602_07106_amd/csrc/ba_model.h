@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kModelBlock<CRC>) void k_gen_model(ModelArgs a)
                 const uint32_t j = 2 * lane + t * (2 * kWave);
                 uint32_t u0, v0, u1, v1;
                 pair_at(j, u0, v0, u1, v1);
-                *reinterpret_cast<uint4 *>(out + 2 * j) = make_uint4(u0, v0, u1, v1);
+                store_edges16(out + 2 * j, u0, v0, u1, v1);
             }
         } else {
             for (uint32_t j = 2 * lane; j < tn; j += 2 * kWave) {
