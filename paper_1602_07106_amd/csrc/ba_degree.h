@@ -452,6 +452,15 @@ __device__ __forceinline__ bool hist_part(const DegArgs &a, uint32_t k, HistPart
     return true;
 }
 
+// 16 bytes of region entries, read once: a non-temporal load, so the reads
+// do not hold L2 lines that the other regions' reads could use.
+__device__ __forceinline__ uint4 load_nt16(const uint4 *p)
+{
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+    return make_uint4(x.x, x.y, x.z, x.w);
+}
+
 // Calls f(x) for every entry x (a 16-bit local index) of the regions the
 // calling wave takes of a part: regions p0 + wv, p0 + wv + 16, ...  Lane j
 // fetches the fill of the wave's j-th region up front (at most kPBlocksMax /
@@ -499,7 +508,7 @@ __device__ __forceinline__ uint32_t hist_visit(const DegArgs &a, const HistPart 
 #pragma unroll
         for (uint32_t k = 0; k < 4; k++) {
             const uint32_t t = lane + 64 * (4 * b + k);
-            B.q[k] = t < R.nv ? vs[t] : make_uint4(0u, 0u, 0u, 0u);
+            B.q[k] = t < R.nv ? load_nt16(vs + t) : make_uint4(0u, 0u, 0u, 0u);
         }
         if (b == 0) {
             const uint32_t x = R.head + R.nv * 8 + lane;
