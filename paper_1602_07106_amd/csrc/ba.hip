@@ -119,34 +119,47 @@ __device__ __forceinline__ void flush_pair(const GenArgs &a, const uint32_t *sta
 }
 
 // Edge-pair output is written once and never read back by the kernel that
-// writes it, so its stores are non-temporal: they stream through L2 instead
-// of taking its lines from data that is still being assembled there (the
-// fused generator's partially written partition regions, which then reach
-// HBM in pieces).
-__device__ __forceinline__ void store_nt(uint32_t *p, uint32_t x) { __builtin_nontemporal_store(x, p); }
+// writes it, so its stores are non-temporal (NT): they stream through L2
+// instead of taking its lines from data that is still being assembled there
+// (the fused generator's partially written partition regions, which then
+// reach HBM in pieces).  The batched generator keeps plain stores: NT
+// measured slower there.
+template <bool NT>
+__device__ __forceinline__ void store_u32(uint32_t *p, uint32_t x)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(x, p);
+    else
+        *p = x;
+}
 
 // (u0, v0, u1, v1) to a 16-byte aligned p.
+template <bool NT = true>
 __device__ __forceinline__ void store_edges16(uint32_t *p, uint32_t u0, uint32_t v0, uint32_t u1, uint32_t v1)
 {
-    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-    const u32x4 x = {u0, v0, u1, v1};
-    __builtin_nontemporal_store(x, reinterpret_cast<u32x4 *>(p));
+    if constexpr (NT) {
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4 x = {u0, v0, u1, v1};
+        __builtin_nontemporal_store(x, reinterpret_cast<u32x4 *>(p));
+    } else {
+        *reinterpret_cast<uint4 *>(p) = make_uint4(u0, v0, u1, v1);
+    }
 }
 
 // Edges j and j+1 (when j+1 < tn) to the output, one 16-byte store when aligned.
-template <bool VEC16>
+template <bool VEC16, bool NT = true>
 __device__ __forceinline__ void store_pair(uint32_t *out, uint32_t j, uint32_t tn, uint32_t u0, uint32_t v0,
                                            uint32_t u1, uint32_t v1)
 {
     const bool two = j + 1 < tn;
     if (VEC16 && two) {
-        store_edges16(out + 2 * j, u0, v0, u1, v1);
+        store_edges16<NT>(out + 2 * j, u0, v0, u1, v1);
     } else {
-        store_nt(out + 2 * j, u0);
-        store_nt(out + 2 * j + 1, v0);
+        store_u32<NT>(out + 2 * j, u0);
+        store_u32<NT>(out + 2 * j + 1, v0);
         if (two) {
-            store_nt(out + 2 * j + 2, u1);
-            store_nt(out + 2 * j + 3, v1);
+            store_u32<NT>(out + 2 * j + 2, u1);
+            store_u32<NT>(out + 2 * j + 3, v1);
         }
     }
 }

@@ -115,16 +115,16 @@ __global__ __launch_bounds__(WAVES * 64) void k_gen_batch(BatchArgs a)
                     const uint32_t jj = 2 * lane + t * (2 * kWave);
                     uint32_t u0, u1, v0, v1;
                     pair(jj, u0, u1, v0, v1);
-                    store_edges16(out + 2 * jj, u0, v0, u1, v1);
+                    store_edges16<false>(out + 2 * jj, u0, v0, u1, v1);
                 }
             } else {
                 for (uint32_t jj = 2 * lane; jj < tn; jj += 2 * kWave) {
                     uint32_t u0, u1, v0, v1;
                     pair(jj, u0, u1, v0, v1);
                     if (vec16)
-                        store_pair<true>(out, jj, tn, u0, v0, u1, v1);
+                        store_pair<true, false>(out, jj, tn, u0, v0, u1, v1);
                     else
-                        store_pair<false>(out, jj, tn, u0, v0, u1, v1);
+                        store_pair<false, false>(out, jj, tn, u0, v0, u1, v1);
                 }
             }
         };
