@@ -76,6 +76,12 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Edges of a tile: min(cap, rest) in 64 bits, then narrowed (at most cap).
+__device__ __forceinline__ uint32_t tile_len(uint32_t cap, uint64_t rest)
+{
+    return rest < cap ? (uint32_t)rest : cap;
+}
+
 
 // floor(x / d) with the divider's kind (a power of two or not) fixed at
 // compile time, so the flush loops carry no per-step branch on it.  x < 2^31
@@ -456,9 +462,9 @@ __global__ __launch_bounds__(kGenBlock) void k_gen_u32(GenArgs a)
 
     for (uint64_t tile = t0; tile < t1; tile++) {
         const uint64_t off = tile * kTile;
-        const uint32_t tn = (uint32_t)min((uint64_t)kTile, a.count - off);
+        const uint32_t tn = tile_len(kTile, a.count - off);
         const uint64_t ibase = a.begin + off;
-        const uint32_t tn2 = tile + 1 < t1 ? (uint32_t)min((uint64_t)kTile, a.count - off - kTile) : 0u;
+        const uint32_t tn2 = tile + 1 < t1 ? tile_len(kTile, a.count - off - kTile) : 0u;
 
         if constexpr (NARROW)
             chain_tile_next<kGenCarry>(stage, tn, tn2, lane, (R)(2 * ibase + 1),
@@ -555,7 +561,7 @@ __global__ __launch_bounds__(kGenBlock) void k_gen_u64(Gen64Args a)
     const uint64_t wstride = (uint64_t)gridDim.x * kGenWaves;
     for (uint64_t c = (uint64_t)blockIdx.x * kGenWaves + wv; c < a.nchunks; c += wstride) {
         const uint64_t off = c * kTile;
-        const uint32_t tn = (uint32_t)min((uint64_t)kTile, a.count - off);
+        const uint32_t tn = tile_len(kTile, a.count - off);
         const uint64_t ibase = a.begin + off;
         uint64_t *out = a.edges + 2 * off;
         chain_tile_visit(

@@ -70,8 +70,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_gen_batch(BatchArgs a)
             I = a.inst[j];
         }
         const uint64_t off = (t - tcur) * TILE;
-        const uint32_t tn = (uint32_t)min((uint64_t)TILE, I.m - off);
-        const uint32_t tn2 = t + 1 < t1 && t + 1 < tnext ? (uint32_t)min((uint64_t)TILE, I.m - off - TILE) : 0u;
+        const uint32_t tn = tile_len(TILE, I.m - off);
+        const uint32_t tn2 = t + 1 < t1 && t + 1 < tnext ? tile_len(TILE, I.m - off - TILE) : 0u;
         if (I.narrow)
             chain_tile_next<kGenCarry>(stage, tn, tn2, lane, (uint32_t)(2 * off + 1),
                                        [&](uint32_t r) { return hash_narrow(r, I.key); },

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kFBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
     // this wave's tile of chunk ch: first edge offset and size
     auto tile_of = [&](uint64_t ch, uint64_t &woff) -> uint32_t {
         woff = ch * kFChunk + (uint64_t)wv * kFTile;
-        return ch < a.nchunks && woff < a.g.count ? (uint32_t)min((uint64_t)kFTile, a.g.count - woff) : 0u;
+        return ch < a.nchunks && woff < a.g.count ? tile_len(kFTile, a.g.count - woff) : 0u;
     };
 
     for (uint64_t ch = blk; ch < a.nchunks; ch += P) {

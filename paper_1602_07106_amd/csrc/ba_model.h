@@ -209,9 +209,9 @@ __global__ __launch_bounds__(kModelBlock<CRC>) void k_gen_model(ModelArgs a)
         };
 
         const uint64_t off = tile * kTile;
-        const uint32_t tn = (uint32_t)min((uint64_t)kTile, a.count - off);
+        const uint32_t tn = tile_len(kTile, a.count - off);
         const uint64_t ibase = a.begin + off;
-        const uint32_t tn2 = tile + 1 < t1 ? (uint32_t)min((uint64_t)kTile, a.count - off - kTile) : 0u;
+        const uint32_t tn2 = tile + 1 < t1 ? tile_len(kTile, a.count - off - kTile) : 0u;
         // 32-bit positions: the stage holds the final position r and the
         // flush maps it to its node, with every lane busy; 64-bit: the node.
         if constexpr (NARROW)
