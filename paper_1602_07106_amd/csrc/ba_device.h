@@ -55,6 +55,17 @@ __device__ __forceinline__ uint64_t mad64(uint32_t a, uint32_t b, uint64_t c)
     return (uint64_t)a * (uint64_t)b + c;
 }
 
+// a * b + c mod 2^64, and whether it carried out of 64 bits: v_mad_u64_u32
+// writes that carry to a lane mask, which the compiler's own lowering of
+// the sum does not use (it recomputes it with a compare).
+__device__ __forceinline__ uint64_t mad64_carry(uint32_t a, uint32_t b, uint64_t c, bool &carry)
+{
+    uint64_t d, mask;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(d), "=s"(mask) : "v"(a), "v"(b), "v"(c));
+    carry = __builtin_amdgcn_inverse_ballot_w64(mask);
+    return d;
+}
+
 // fmix64 after its first xor-shift, on (lo, hi) halves: multiply by C1,
 // xor-shift 27, multiply by C2, xor-shift 31.  `hi_c1` is the already
 // accumulated high-word contribution of the first multiply's hi*C1lo term.
@@ -95,11 +106,16 @@ __device__ __forceinline__ uint64_t hash_bounded(uint64_t r, uint64_t b, const H
     lo ^= shr64_lo(hi, lo, 30);
     hi ^= hi >> 30;
     fmix_tail(lo, hi, hi * kC1Lo);
-    // umul64hi((hi:lo), (b1:b0))
+    // umul64hi((hi:lo), (b1:b0)) = hi*b1 + floor((hi*b0 + t) / 2^32), with
+    // t = lo*b1 + mulhi(lo, b0) < 2^64.  hi*b0 + t can carry out of 64 bits;
+    // the carry is bit 32 of that quotient, taken from the multiply-add's own
+    // carry-out, so all of t is added at once and no 32-bit half has to be
+    // copied into a fresh register pair.
     const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
-    uint64_t t = mad64(lo, b1, __umulhi(lo, b0));
-    uint64_t u = mad64(hi, b0, (uint32_t)t);
-    return mad64(hi, b1, (t >> 32) + (u >> 32));
+    const uint64_t t = mad64(lo, b1, __umulhi(lo, b0));
+    bool carry;
+    const uint64_t w = mad64_carry(hi, b0, t, carry);
+    return mad64(hi, b1, (w >> 32) | (carry ? (uint64_t)1 << 32 : 0));
 }
 
 // h(r) for any 64-bit r >= 1.

@@ -61,6 +61,15 @@ __device__ __forceinline__ uint64_t shalf64(uint64_t x, const Divider &v)
     return sdiv64<false>(x >> 1, v);
 }
 
+// The checksum word of the edge with start position r0 = 2i + 1 and
+// endpoints (u, v): ((u << 32) + v) * r0 mod 2^64.  Node IDs are below 2^32,
+// so the word is u:v and only the low halves of the cross products count.
+__device__ __forceinline__ uint64_t edge_word(uint64_t u, uint64_t v, uint64_t r0)
+{
+    const uint32_t r0l = (uint32_t)r0, r0h = (uint32_t)(r0 >> 32);
+    return mad64((uint32_t)v, r0l, 0) + ((uint64_t)((uint32_t)v * r0h + (uint32_t)u * r0l) << 32);
+}
+
 // One wave's run of tn edges starting at edge ibase: the chain of every
 // edge, its second endpoint counted (cnt: LDS counters of nodes below klds;
 // deg: global counts of nodes below k) and its checksum word XORed into xs.
@@ -89,7 +98,7 @@ __device__ __forceinline__ void stream_run16(const HashKey &key, const Divider &
                 atomicAdd(&cnt[v], 1u);
             else if (v < k)
                 __hip_atomic_fetch_add(deg + v, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            xs ^= ((u << 32) + v) * (uint64_t)r0;
+            xs ^= edge_word(u, v, r0);
         });
 }
 
@@ -213,7 +222,7 @@ __device__ __forceinline__ void stream_run_packed(const HashKey &key, const Divi
         } else if (v < k) {
             __hip_atomic_fetch_add(deg + v, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        xs ^= ((u << 32) + v) * (uint64_t)r0;
+        xs ^= edge_word(u, v, r0);
     };
 
     // Every lane runs two chains (A and B): their hash evaluations are
