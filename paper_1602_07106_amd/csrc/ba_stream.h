@@ -62,18 +62,23 @@ __device__ __forceinline__ uint64_t shalf64(uint64_t x, const Divider &v)
 }
 
 // The checksum word of the edge with start position r0 = 2i + 1 and
-// endpoints (u, v): ((u << 32) + v) * r0 mod 2^64.  Node IDs are below 2^32,
-// so the word is u:v and only the low halves of the cross products count.
+// endpoints (u, v): ((u << 32) + v) * r0 mod 2^64, from 32-bit halves.  The
+// word's low half is v's and its high half is u + (v >> 32) mod 2^32, or u's
+// alone when every node ID is below 2^32 (ID32: n <= 2^32); only the low
+// halves of the cross products reach the result.
+template <bool ID32>
 __device__ __forceinline__ uint64_t edge_word(uint64_t u, uint64_t v, uint64_t r0)
 {
+    const uint32_t xl = (uint32_t)v, xh = ID32 ? (uint32_t)u : (uint32_t)u + (uint32_t)(v >> 32);
     const uint32_t r0l = (uint32_t)r0, r0h = (uint32_t)(r0 >> 32);
-    return mad64((uint32_t)v, r0l, 0) + ((uint64_t)((uint32_t)v * r0h + (uint32_t)u * r0l) << 32);
+    return mad64(xl, r0l, 0) + ((uint64_t)(xl * r0h + xh * r0l) << 32);
 }
 
 // One wave's run of tn edges starting at edge ibase: the chain of every
 // edge, its second endpoint counted (cnt: LDS counters of nodes below klds;
 // deg: global counts of nodes below k) and its checksum word XORed into xs.
-template <bool NARROW, bool POW2>
+// ID32: every node ID is below 2^32 (always so for 32-bit positions).
+template <bool NARROW, bool POW2, bool ID32 = NARROW>
 __device__ __forceinline__ void stream_run16(const HashKey &key, const Divider &div, uint64_t ibase, uint32_t tn,
                                              uint32_t klds, uint64_t k, uint32_t *cnt, uint64_t *deg, uint64_t &xs)
 {
@@ -98,7 +103,7 @@ __device__ __forceinline__ void stream_run16(const HashKey &key, const Divider &
                 atomicAdd(&cnt[v], 1u);
             else if (v < k)
                 __hip_atomic_fetch_add(deg + v, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            xs ^= edge_word(u, v, r0);
+            xs ^= edge_word<ID32>(u, v, r0);
         });
 }
 
@@ -111,7 +116,7 @@ __device__ __forceinline__ void stream_xor_out(uint64_t xs, uint64_t *cs)
     }
 }
 
-template <bool NARROW, bool POW2>
+template <bool NARROW, bool POW2, bool ID32>
 __global__ __launch_bounds__(kStreamBlock) void k_stream(StreamArgs a)
 {
     __shared__ uint32_t cnt[kLdsNodes];
@@ -126,7 +131,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream(StreamArgs a)
     if (w0 < a.count) {
         // per_wave < 2^32: the host splits larger launches
         const uint32_t tn = (uint32_t)min(a.per_wave, a.count - w0);
-        stream_run16<NARROW, POW2>(a.key, a.div, a.begin + w0, tn, a.klds, a.k, cnt, a.deg, xs);
+        stream_run16<NARROW, POW2, ID32>(a.key, a.div, a.begin + w0, tn, a.klds, a.k, cnt, a.deg, xs);
     }
     stream_xor_out(xs, a.cs);
     __syncthreads();
@@ -176,7 +181,7 @@ __device__ __forceinline__ void packed_flush(uint32_t *cnt, uint32_t ktier, uint
 // LDS counters cnt, of nodes below k in deg, checksum words into xs.  The
 // wave takes exactly `rounds` block barriers (at least its own claims /
 // kStreamRoundClaims), so every wave of the block must pass the same rounds.
-template <bool NARROW, bool POW2>
+template <bool NARROW, bool POW2, bool ID32 = NARROW>
 __device__ __forceinline__ void stream_run_packed(const HashKey &key, const Divider &div, uint64_t ibase, uint32_t tot,
                                                   uint32_t ktier, uint64_t k, uint32_t *cnt, uint64_t *deg,
                                                   uint64_t rounds, uint64_t &xs)
@@ -222,7 +227,7 @@ __device__ __forceinline__ void stream_run_packed(const HashKey &key, const Divi
         } else if (v < k) {
             __hip_atomic_fetch_add(deg + v, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        xs ^= edge_word(u, v, r0);
+        xs ^= edge_word<ID32>(u, v, r0);
     };
 
     // Every lane runs two chains (A and B): their hash evaluations are
@@ -300,7 +305,7 @@ __device__ __forceinline__ void stream_run_packed(const HashKey &key, const Divi
     for (; bars < rounds; bars++) lds_barrier();
 }
 
-template <bool NARROW, bool POW2>
+template <bool NARROW, bool POW2, bool ID32>
 __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
 {
     __shared__ uint32_t cnt[kPackedNodes / 2];  // node v: word v >> 1, half v & 1
@@ -314,7 +319,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_stream_packed(StreamArgs a)
     const uint32_t tot = w0 < a.count ? (uint32_t)min(a.per_wave, a.count - w0) : 0u;
     const uint32_t ktier = a.klds;  // min(first_k, 65536)
     uint64_t xs = 0;
-    stream_run_packed<NARROW, POW2>(a.key, a.div, a.begin + w0, tot, ktier, a.k, cnt, a.deg, a.rounds, xs);
+    stream_run_packed<NARROW, POW2, ID32>(a.key, a.div, a.begin + w0, tot, ktier, a.k, cnt, a.deg, a.rounds, xs);
     stream_xor_out(xs, a.cs);
     __syncthreads();
     packed_flush(cnt, ktier, a.deg);
@@ -448,11 +453,11 @@ static int launch_stream_slices(const StreamArgs &a0, uint64_t max_waves, unsign
 }
 
 // 16K tier: a block's LDS counts stay below 16 * 2^27 = 2^31.
-template <bool N, bool P>
+template <bool N, bool P, bool I>
 static int launch_stream_one(const StreamArgs &a0, hipStream_t st)
 {
     uint32_t grid0 = 0;
-    int rc = persistent_grid(k_stream<N, P>, kStreamBlock, &grid0);
+    int rc = persistent_grid(k_stream<N, P, I>, kStreamBlock, &grid0);
     if (rc) return rc;
     const uint64_t max_waves = (uint64_t)grid0 * kStreamWaves;
     return launch_stream_slices(a0, max_waves, 27, [&](StreamArgs a) {
@@ -463,16 +468,16 @@ static int launch_stream_one(const StreamArgs &a0, hipStream_t st)
         const uint64_t waves = (a.count + per_wave - 1) / per_wave;
         const uint32_t grid = (uint32_t)((waves + kStreamWaves - 1) / kStreamWaves);
         return launch_timed(BA_KT_STREAM, st,
-                            [&] { hipLaunchKernelGGL((k_stream<N, P>), dim3(grid), dim3(kStreamBlock), 0, st, a); });
+                            [&] { hipLaunchKernelGGL((k_stream<N, P, I>), dim3(grid), dim3(kStreamBlock), 0, st, a); });
     });
 }
 
 // 64K tier: a wave's share stays below 2^30 edges (32-bit claim counters).
-template <bool N, bool P>
+template <bool N, bool P, bool I>
 static int launch_stream_packed(const StreamArgs &a0, hipStream_t st)
 {
     uint32_t grid0 = 0;
-    int rc = persistent_grid(k_stream_packed<N, P>, kStreamBlock, &grid0);
+    int rc = persistent_grid(k_stream_packed<N, P, I>, kStreamBlock, &grid0);
     if (rc) return rc;
     const uint64_t max_waves = (uint64_t)grid0 * kStreamWaves;
     return launch_stream_slices(a0, max_waves, 30, [&](StreamArgs a) {
@@ -485,7 +490,7 @@ static int launch_stream_packed(const StreamArgs &a0, hipStream_t st)
         const uint32_t grid = (uint32_t)((waves + kStreamWaves - 1) / kStreamWaves);
         a.klds = (uint32_t)(a.k < kPackedNodes ? a.k : kPackedNodes);
         return launch_timed(BA_KT_STREAM, st,
-                            [&] { hipLaunchKernelGGL((k_stream_packed<N, P>), dim3(grid), dim3(kStreamBlock), 0, st, a); });
+                            [&] { hipLaunchKernelGGL((k_stream_packed<N, P, I>), dim3(grid), dim3(kStreamBlock), 0, st, a); });
     });
 }
 
@@ -521,13 +526,18 @@ static int launch_stream(uint64_t n, uint64_t begin, uint64_t count, uint32_t d,
     a.deg = deg;
     a.cs = cs;
     const bool narrow = 2 * (begin + count) <= ((uint64_t)1 << 32);
+    const bool id32 = n <= ((uint64_t)1 << 32);  // every node ID below 2^32 (implied by narrow)
     const bool pow2 = a.div.pow2 != 0;
-    if (stream_tier(n, k, narrow, tier) == BA_TIER_64K) {
-        if (narrow) return pow2 ? launch_stream_packed<true, true>(a, st) : launch_stream_packed<true, false>(a, st);
-        return pow2 ? launch_stream_packed<false, true>(a, st) : launch_stream_packed<false, false>(a, st);
-    }
-    if (narrow) return pow2 ? launch_stream_one<true, true>(a, st) : launch_stream_one<true, false>(a, st);
-    return pow2 ? launch_stream_one<false, true>(a, st) : launch_stream_one<false, false>(a, st);
+    const bool packed = stream_tier(n, k, narrow, tier) == BA_TIER_64K;
+    auto go = [&](auto n_, auto p_, auto i_) {
+        constexpr bool N = decltype(n_)::value, P = decltype(p_)::value, I = decltype(i_)::value;
+        return packed ? launch_stream_packed<N, P, I>(a, st) : launch_stream_one<N, P, I>(a, st);
+    };
+    using T = std::true_type;
+    using F = std::false_type;
+    if (narrow) return pow2 ? go(T{}, T{}, T{}) : go(T{}, F{}, T{});
+    if (id32) return pow2 ? go(F{}, T{}, T{}) : go(F{}, F{}, T{});
+    return pow2 ? go(F{}, T{}, F{}) : go(F{}, F{}, F{});
 }
 
 }  // namespace ba

@@ -193,6 +193,25 @@ def test_streaming_ranges_accumulate_including_wide_positions():
 
 
 @pytest.mark.parametrize("tier", [ba.TIER_16K, ba.TIER_64K])
+def test_streaming_ranges_with_node_ids_past_2_32(tier):
+    # n > 2^32: endpoints at and above 2^32 enter the checksum word
+    # (u * 2^32 + v) with their high words; positions near 2^63 and 2^64 make
+    # the wide hash's 64x64 high product carry out of its 64-bit partial sum
+    k = 1000
+    for n, d, seed in [((1 << 33) + 3, 1, 9), (1 << 40, 1 << 21, 13), (1 << 33, (1 << 30) - 1, 21)]:
+        m = n * d
+        for b, c in [(m - 3000, 3000), (m // 2 - 1500, 3000), (m // 3, 2000)]:
+            _say("degrees range past 2^32", n, d, seed, b, c, tier)
+            deg = torch.zeros(k, dtype=torch.int64, device="cuda")
+            cs = torch.zeros(1, dtype=torch.int64, device="cuda")
+            ba.degrees_range(n, d, seed, b, c, k, deg, cs, tier=tier)
+            torch.cuda.synchronize()
+            ref, rcs, _ = oracle.stream(d, seed, b, c, k)
+            assert np.array_equal(_u64(deg), ref)
+            assert (int(cs.item()) & M64) == rcs
+
+
+@pytest.mark.parametrize("tier", [ba.TIER_16K, ba.TIER_64K])
 @pytest.mark.parametrize("n,d,seed,k", [(100000, 4, 1, 100000), (20000, 5, 3, 1000), (70001, 9, 77, 65537),
                                         (3000, 2, 5, 3000)])
 def test_streaming_degrees_on_either_lds_tier(tier, n, d, seed, k):
@@ -357,8 +376,11 @@ def test_extreme_parameters_sampled():
     # d = 2^31 with n = 1: the largest power-of-two divisor on 32-bit positions;
     # n = 3, d = 715827882: a large odd-factor divisor with edge indices up to
     # 2^31 - 3 on 32-bit positions (the 31-bit-numerator division)
+    # positions near 2^63 and 2^64 (n = 2^40, d = 2^21; n = 2^33, d = 2^30 - 1):
+    # the wide hash's high product carries out of its 64-bit partial sum
     cases = [((1 << 32), 2, 5), ((1 << 32), 1, M64), (3, (1 << 31) - 1, 0), (5, (1 << 30) + 7, 77),
-             ((1 << 33) + 3, 1, 9), (1, 1 << 31, 3), (3, 715827882, 11)]
+             ((1 << 33) + 3, 1, 9), (1, 1 << 31, 3), (3, 715827882, 11), (1 << 40, 1 << 21, 13),
+             (1 << 33, (1 << 30) - 1, 21)]
     for n, d, seed in cases:
         m = n * d
         for b in [0, m // 2 - 1000, m - 2000]:
