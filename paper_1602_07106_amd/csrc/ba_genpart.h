@@ -6,7 +6,7 @@
 // edge IDs.  Each wave runs the chain loop (paper Section 2, figure
 // generateEdge) over its kFTile edges into its part of the block's LDS stage,
 // writes the edge pairs as the plain generator does, and keeps the second
-// endpoints of its edges in registers (22 a lane).  The block then
+// endpoints of its edges in registers (20 a lane).  The block then
 // counting-sorts the chunk's second endpoints by sub-bucket in the same LDS
 // (the stage is free again) and appends each sub-bucket's run of 16-bit local
 // indices to the block's own region for it, exactly the layout k_deg_part
@@ -22,8 +22,8 @@
 // range would not: the targets of early edges all fall in the lowest
 // sub-buckets, whose regions then overflow into global atomics.
 //
-// Run length is what matters for the sort: a chunk's 22528 second endpoints
-// over 1024 sub-buckets leave runs of about 22 entries (44 bytes) per region
+// Run length is what matters for the sort: a chunk's 20480 second endpoints
+// over 1024 sub-buckets leave runs of about 20 entries (40 bytes) per region
 // and chunk; shorter runs (smaller chunks, or 32768-node sub-buckets) cost
 // more in scattered stores than the overlap of two smaller blocks per
 // compute unit gains.
@@ -33,8 +33,8 @@ namespace ba {
 
 constexpr uint32_t kFWaves = 16;
 constexpr uint32_t kFBlock = kFWaves * kWave;   // 1024 threads, one block per compute unit (121 KiB of LDS)
-constexpr uint32_t kFTile = 1408;               // edges per wave per chunk (a multiple of 128)
-constexpr uint32_t kFChunk = kFWaves * kFTile;  // 22528 edges per block chunk
+constexpr uint32_t kFTile = 1280;               // edges per wave per chunk (a multiple of 128)
+constexpr uint32_t kFChunk = kFWaves * kFTile;  // 20480 edges per block chunk
 constexpr uint32_t kFPer = kFTile / kWave;      // second endpoints per thread
 constexpr uint32_t kFBins = kWin16 / kFBlock;   // sub-buckets per thread in the scan
 constexpr uint32_t kFCarry = 256;               // next-tile edges a wave's chain tail may claim
