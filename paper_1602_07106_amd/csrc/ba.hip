@@ -127,9 +127,10 @@ __device__ __forceinline__ void flush_pair(const GenArgs &a, const uint32_t *sta
 // Edge-pair output is written once and never read back by the kernel that
 // writes it, so its stores are non-temporal (NT): they stream through L2
 // instead of taking its lines from data that is still being assembled there
-// (the fused generator's partially written partition regions, which then
-// reach HBM in pieces).  The batched generator keeps plain stores: NT
-// measured slower there.
+// (the fused generator's partially written partition regions; with plain
+// pair stores those cost the fused kernel about 0.4 ms more, for the same
+// HBM bytes).  The batched generator keeps plain stores: NT measured slower
+// there.
 template <bool NT>
 __device__ __forceinline__ void store_u32(uint32_t *p, uint32_t x)
 {
